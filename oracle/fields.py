@@ -1,0 +1,167 @@
+"""Field arithmetic for the oracle (test infrastructure only).
+
+Three fields share one interface so that the recursion in ``oracle.bg`` is
+written once:
+
+* ``Fp(p)``      -- the prime field Z_p, elements are Python ints in [0, p).
+                    The paper fixes p < 2^31 with default p = 2^31 - 19
+                    (Sec. 3, finite-field representation); the oracle accepts
+                    any odd prime.  Inverse by Fermat, x^(p-2) mod p; the
+                    paper uses the extended Euclidean algorithm (Sec. 3), and
+                    the inverse is unique, so both give the same residue.
+* ``Complex128`` -- Python ``complex`` (IEEE binary64 real and imaginary parts),
+                    the double-precision complex path of the paper (Sec. 3).
+* ``Rationals``  -- ``fractions.Fraction``, exact; used to arbitrate FP64
+                    rounding and to tie the two other fields together.
+
+Minkowski products use the mostly-minus metric diag(+1, -1, ..., -1) of
+Sec. 2.3 (the completeness relation is written with the "mostly negative
+metric"), bilinear (no complex conjugation).
+
+Parity: pinned.  F_p ops against Python's own integer arithmetic and
+``pow(x, -1, p)``; Q ops against ``fractions``; see tests/test_oracle_fields.py.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+
+def is_prime(p: int) -> bool:
+    """Deterministic trial division (oracle side; fine for p < 2^31)."""
+    if p < 2:
+        return False
+    if p % 2 == 0:
+        return p == 2
+    f = 3
+    while f * f <= p:
+        if p % f == 0:
+            return False
+        f += 2
+    return True
+
+
+class Fp:
+    """Z_p with canonical representatives in [0, p)."""
+
+    name = "fp"
+    exact = True
+
+    def __init__(self, p: int):
+        if not is_prime(p) or p == 2:
+            raise ValueError(f"{p} is not an odd prime")
+        self.p = p
+
+    def __repr__(self):
+        return f"Fp({self.p})"
+
+    def elem(self, x) -> int:
+        if isinstance(x, Fraction):
+            return (x.numerator * pow(x.denominator, self.p - 2, self.p)) % self.p
+        return int(x) % self.p
+
+    zero = 0
+    one = 1
+
+    def add(self, a, b):
+        return (a + b) % self.p
+
+    def sub(self, a, b):
+        return (a - b) % self.p
+
+    def mul(self, a, b):
+        return (a * b) % self.p
+
+    def neg(self, a):
+        return (-a) % self.p
+
+    def inv(self, a):
+        if a % self.p == 0:
+            raise ZeroDivisionError("inverse of 0 in F_p")
+        return pow(a, self.p - 2, self.p)
+
+    def is_zero(self, a) -> bool:
+        return a % self.p == 0
+
+
+class Complex128:
+    """IEEE binary64 complex numbers (Python ``complex``)."""
+
+    name = "c128"
+    exact = False
+    zero = 0j
+    one = 1 + 0j
+
+    def elem(self, x) -> complex:
+        return complex(x)
+
+    def add(self, a, b):
+        return a + b
+
+    def sub(self, a, b):
+        return a - b
+
+    def mul(self, a, b):
+        return a * b
+
+    def neg(self, a):
+        return -a
+
+    def inv(self, a):
+        if a == 0:
+            raise ZeroDivisionError("inverse of 0 in C")
+        return 1 / a
+
+    def is_zero(self, a) -> bool:
+        return a == 0
+
+
+class Rationals:
+    """Exact rationals; complex values are not needed on this field."""
+
+    name = "q"
+    exact = True
+    zero = Fraction(0)
+    one = Fraction(1)
+
+    def elem(self, x) -> Fraction:
+        return Fraction(x)
+
+    def add(self, a, b):
+        return a + b
+
+    def sub(self, a, b):
+        return a - b
+
+    def mul(self, a, b):
+        return a * b
+
+    def neg(self, a):
+        return -a
+
+    def inv(self, a):
+        if a == 0:
+            raise ZeroDivisionError("inverse of 0 in Q")
+        return 1 / a
+
+    def is_zero(self, a) -> bool:
+        return a == 0
+
+
+def mdot(F, x, y):
+    """Bilinear Minkowski product x.y = x^0 y^0 - sum_{mu>=1} x^mu y^mu."""
+    s = F.mul(x[0], y[0])
+    for mu in range(1, len(x)):
+        s = F.sub(s, F.mul(x[mu], y[mu]))
+    return s
+
+
+def vadd(F, x, y):
+    return [F.add(a, b) for a, b in zip(x, y)]
+
+
+def vsub(F, x, y):
+    return [F.sub(a, b) for a, b in zip(x, y)]
+
+
+def vscale(F, c, x):
+    return [F.mul(c, a) for a in x]

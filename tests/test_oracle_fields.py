@@ -1,0 +1,67 @@
+"""Pins for oracle.fields: the field operations against textbook definitions."""
+import random
+from fractions import Fraction
+
+import pytest
+
+from oracle import fields
+
+P_DEFAULT = 2147483629  # 2^31 - 19, the paper's default prime (Sec. 3)
+PRIMES = [P_DEFAULT, 2147483647, 1000000007, 10007, 97]
+
+
+def test_primality_of_known_values():
+    for p in PRIMES:
+        assert fields.is_prime(p)
+    for c in [1, 4, 9, 2147483627, 2147483649, 10007 * 97]:
+        assert not fields.is_prime(c)
+    assert P_DEFAULT == 2**31 - 19
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_fp_ops_match_python_ints(p):
+    F = fields.Fp(p)
+    rng = random.Random(p)
+    edge = [0, 1, 2, p - 2, p - 1]
+    vals = edge + [rng.randrange(p) for _ in range(200)]
+    for a in vals[:40]:
+        for b in vals:
+            assert F.add(a, b) == (a + b) % p
+            assert F.sub(a, b) == (a - b) % p
+            assert F.mul(a, b) == (a * b) % p
+    for a in vals:
+        if a:
+            inv = F.inv(a)
+            assert inv == pow(a, -1, p)           # Python's own modular inverse
+            assert (a * inv) % p == 1
+    with pytest.raises(ZeroDivisionError):
+        F.inv(0)
+
+
+def test_fp_rejects_non_primes():
+    with pytest.raises(ValueError):
+        fields.Fp(2147483631)   # 2^31 - 17 = 3 * 715827877
+    with pytest.raises(ValueError):
+        fields.Fp(2)
+
+
+def test_fraction_to_fp_reduction():
+    F = fields.Fp(P_DEFAULT)
+    x = Fraction(-7, 13)
+    assert (F.elem(x) * 13) % P_DEFAULT == (-7) % P_DEFAULT
+
+
+def test_minkowski_product_signature():
+    for F in (fields.Fp(97), fields.Complex128(), fields.Rationals()):
+        e = [[F.elem(int(m == mu)) for m in range(5)] for mu in range(5)]
+        assert fields.mdot(F, e[0], e[0]) == F.one
+        for mu in range(1, 5):
+            assert fields.mdot(F, e[mu], e[mu]) == F.neg(F.one)
+            assert fields.mdot(F, e[0], e[mu]) == F.zero
+
+
+def test_mdot_is_bilinear_not_sesquilinear():
+    C = fields.Complex128()
+    x = [1j, 2.0, 0.0, 1.0]
+    # x.x = (i)^2 - 4 - 0 - 1 = -6 (no conjugation)
+    assert fields.mdot(C, x, x) == -6
