@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the batched Berends-Giele recursion on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one pass of the hot path over one batch resident in HBM: one call
+of bg_amplitudes_c128 on the n = 8, d = 4 complex128 workload (2^20
+phase-space points: RAMBO momenta at sqrt(s) = 1000, uniform random
+helicities, random null reference per point).  The same line carries the
+n = 8, d = 6 F_p workload (p = 2^31 - 19, 2^20 points) measured the same way.
+
+Prints one JSON line.  Kernel durations are taken with HIP events recorded on
+the stream the kernels run on, around every launch.  The roofline figure
+uses the algorithmic work per amplitude, W = d (6 C(n,3) + 4 C(n,4) + 2 R + 1)
+field multiply-adds with R = (n-1)(n-2)/2 - 1 propagators; a complex
+multiply-add is 8 FP64 flops, an F_p multiply-add at least one 32x32->64-bit
+integer multiply-add issue.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64
+INT_MAD_PEAK_TOPS = 39.3         # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one v_mad_u64_u32 per lane-cycle
+
+
+def work_per_amplitude(n: int, d: int) -> int:
+    R = (n - 1) * (n - 2) // 2 - 1
+    return d * (6 * math.comb(n, 3) + 4 * math.comb(n, 4) + 2 * R + 1)
+
+
+def time_launches(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_all0.record()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    t_all1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_all0.elapsed_time(t_all1)
+    per = [a.elapsed_time(b) for a, b in ev]
+    return total_ms, sum(per) / len(per), wall
+
+
+def cpu_baseline(kind: str, npts: int):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import multiprocessing as mp
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import bgtest
+    from paper_2502_07060_amd import inputs as I
+
+    w = I.config_workload(kind, npts=npts)
+    k, e = w["k"], w["eps"]
+    cores = bgtest._workers()
+    bgtest.pool()  # start workers before timing
+    t0 = time.perf_counter()
+    if w["field"] == "fp":
+        bgtest.oracle_fp(k.astype(np.int64), e.astype(np.int64), w["p"])
+    else:
+        bgtest.oracle_c(k, e)
+    dt = time.perf_counter() - t0
+    return {"value": npts / dt, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{npts} points of {kind} drawn with the same recipe and seed, pure-Python oracle, "
+                      f"{cores} worker processes, {dt:.1f} s wall"}
+
+
+def run_workload(kind: str, steps: int, warmup: int):
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    w = I.config_workload(kind)
+    dev = torch.device("cuda:0")
+    n, d = w["n"], w["d"]
+    npts = len(w["k"])
+    if w["field"] == "fp":
+        tk = torch.from_numpy(I.to_soa(w["k"]).view(np.int32)).to(dev)
+        te = torch.from_numpy(I.to_soa(w["eps"]).view(np.int32)).to(dev)
+        out = torch.empty(npts, dtype=torch.int32, device=dev)
+        st = torch.empty(npts, dtype=torch.uint8, device=dev)
+        fn = lambda: bg.bg_amplitudes_fp(tk, te, w["p"], out=out, status=st)
+    else:
+        tk = torch.from_numpy(I.to_soa(w["k"])).to(dev)
+        te = torch.from_numpy(I.to_soa(w["eps"])).to(dev)
+        out = torch.empty(npts, dtype=torch.complex128, device=dev)
+        st = torch.empty(npts, dtype=torch.uint8, device=dev)
+        fn = lambda: bg.bg_amplitudes_c128(tk, te, out=out, status=st)
+    total_ms, launch_ms, wall = time_launches(fn, steps, warmup)
+    bad = int((st != 0).sum().item())
+    W = work_per_amplitude(n, d)
+    if w["field"] == "fp":
+        achieved = W * npts / (launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": INT_MAD_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT_MAD_PEAK_TOPS, "traffic": None}
+    else:
+        achieved = 8 * W * npts / (launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    return {
+        "value": npts * steps / (total_ms * 1e-3),
+        "ms_per_step": total_ms / steps,
+        "kernel_ms": launch_ms,
+        "host_wall_ms_per_step": 1e3 * wall / steps,
+        "npts": npts, "n": n, "d": d, "field": w["field"], "nonzero_status": bad,
+        "work_per_amplitude": W, "roofline": roof,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=6144)
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the recursion shards by point range with no "
+              "communication, so the single-GPU figure is the per-rank figure", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    main_run = run_workload("c8_d4", a.steps, a.warmup)
+    fp_run = run_workload("fp8_d6", a.steps, a.warmup)
+    line = {
+        "metric": "amplitudes/s at n=8 (C d=4, F_p d=6); served p50/p99 latency vs plain launch",
+        "value": main_run["value"],
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": "c8_d4: n=8 gluons, d=4, complex128, 2^20 phase-space points "
+                        "(RAMBO sqrt(s)=1000, uniform random helicities, random null reference)",
+            "npts": main_run["npts"], "n": 8, "d": 4,
+        },
+        "roofline": main_run["roofline"],
+        "kernel_ms": main_run["kernel_ms"],
+        "fp8_d6": {
+            "workload": "n=8 gluons, d=6, Z_p p=2^31-19 (uint32), 2^20 points, light-cone momenta "
+                        "with closing pair, transverse random polarisations",
+            "value": fp_run["value"], "unit": "amplitudes/s", "dtype": "int32 Montgomery (int64 accumulate)",
+            "ms_per_step": fp_run["ms_per_step"], "kernel_ms": fp_run["kernel_ms"],
+            "roofline": fp_run["roofline"], "nonzero_status": fp_run["nonzero_status"],
+        },
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline("c8_d4", a.cpu_sample)
+        line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,126 @@
+/*
+ * bg.h -- C ABI of the MI355X (gfx950) Berends-Giele library libbg_mi355x.so.
+ *
+ * The library evaluates colour-ordered n-gluon tree amplitudes with the
+ * Berends-Giele recursion of arXiv:2502.07060 (Sec. 2.2: the current
+ * recursion, the three- and four-gluon vertices V3 and V4, the sub-range
+ * momenta P_{i,j}), for many phase-space points at once, over two fields:
+ *
+ *   bg_amplitudes_c128  complex numbers in IEEE binary64 (the paper's
+ *                       double-precision complex path, Sec. 3);
+ *   bg_amplitudes_fp    the prime field Z_p, p an odd prime below 2^31 (the
+ *                       paper's finite-field path, Sec. 3, default
+ *                       p = 2^31 - 19), results exact.
+ *
+ * What is returned.  Legs 1..n carry momenta k_l and polarisation vectors
+ * eps_l, each with d components, metric diag(+1,-1,...,-1) (Sec. 2.3),
+ * products bilinear (no complex conjugation).  With N = n - 1 and currents
+ * J(S) over the contiguous sub-ranges S of legs 1..N, J([l]) = eps_l and
+ *     J(S) = K(S) / P_S^2,
+ *     K(S) = sum over splits S = A|B of
+ *              (J_A.J_B)(P_A - P_B) + 2 (P_B.J_A) J_B - 2 (P_A.J_B) J_A
+ *          + sum over splits S = A|B|C of
+ *              2 (J_A.J_C) J_B - (J_A.J_B) J_C - (J_B.J_C) J_A,
+ * which is the paper's recursion with the factor i of each vertex cancelled
+ * against the -i of each propagator.  The value returned per point is
+ *     M = eps_n . K([1..N]),
+ * the amplitude built from the (n-1)-point current with the off-shell
+ * propagator removed (Sec. 2.2); the amplitude with all phases is A = i M.
+ * k_n is never read (it enters only through momentum conservation, which the
+ * caller's momenta are expected to satisfy; nothing is checked).
+ *
+ * Data layout (all compute entry points).  Arrays are device pointers owned
+ * by the caller (for example torch tensors); nothing is retained after the
+ * call returns:
+ *     momenta[l][mu][q], pols[l][mu][q]   l < n, mu < d, q < ld, q fastest;
+ *     element (l, mu, q) at offset (l * d + mu) * ld + q elements.
+ * For complex128 an element is two doubles (real, imaginary).  out[q] and
+ * status[q] for q < npts.  ld >= npts.
+ *
+ * Per-point status byte (status may be NULL):
+ *     BG_PT_OK         0  result valid
+ *     BG_PT_SINGULAR   1  some propagator denominator P_S^2 is exactly zero
+ *                         (2 <= |S| <= n-2); out[q] is the sentinel
+ *     BG_PT_BADRESIDUE 2  (F_p) a component of k_1..k_{n-1} or eps_1..eps_n
+ *                         is >= p; out[q] is the sentinel (takes precedence)
+ * Sentinels: NaN + i NaN (complex128), 0xFFFFFFFF (F_p).
+ *
+ * Errors.  Argument errors are reported by a negative return value before
+ * anything is enqueued.  A failed kernel launch returns BG_EHIP.  Calls are
+ * asynchronous on the given HIP stream (NULL = the default stream): results
+ * are valid once the stream has been synchronised.  npts == 0 is a no-op.
+ * The compute entry points allocate no device memory and are thread safe.
+ */
+#ifndef BG_MI355X_H
+#define BG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BG_OK = 0,
+  BG_EINVAL = -1,      /* NULL pointer, ld < npts, npts < 0, bad field tag  */
+  BG_EDOMAIN = -2,     /* n outside [3, BG_MAX_N] or d outside [1, BG_MAX_D] */
+  BG_ENOTPRIME = -3,   /* p not an odd prime below 2^31                      */
+  BG_EHIP = -4,        /* a HIP runtime call or kernel launch failed         */
+  BG_ENOTIMPL = -5,    /* no kernel for this (field, n, d)                   */
+  BG_ENOMEM = -6,      /* a request does not fit the serving budget          */
+  BG_EBUSY = -7        /* serving queue full; retry later                    */
+};
+
+enum { BG_PT_OK = 0, BG_PT_SINGULAR = 1, BG_PT_BADRESIDUE = 2 };
+
+#define BG_MAX_N 14
+#define BG_MAX_D 10
+
+/* Field tags for the batched and serving entry points. */
+enum { BG_FIELD_C128 = 0, BG_FIELD_FP = 1 };
+
+/*
+ * bg_amplitudes_c128 -- amplitudes over complex binary64 (paper Sec. 2.2,
+ * Sec. 3 double-precision complex path).
+ *   n        number of gluons, 3 <= n <= BG_MAX_N
+ *   d        number of momentum components, 1 <= d <= BG_MAX_D (d = 4 is
+ *            four-dimensional; d > 4 states padded with zeros give the
+ *            four-dimensional result, Sec. 2.3)
+ *   npts     number of phase-space points (>= 0)
+ *   ld       leading dimension of momenta and pols (>= npts)
+ *   momenta  device, complex128 [n][d][ld] (re, im interleaved)
+ *   pols     device, complex128 [n][d][ld]
+ *   out      device, complex128 [npts]: M per point
+ *   status   device, uint8 [npts] or NULL
+ *   hip_stream  hipStream_t or NULL
+ * Returns BG_OK or a negative error code.
+ */
+int bg_amplitudes_c128(int n, int d, int64_t npts, int64_t ld,
+                       const double* momenta, const double* pols,
+                       double* out, uint8_t* status, void* hip_stream);
+
+/*
+ * bg_amplitudes_fp -- amplitudes over Z_p (paper Sec. 2.2; Sec. 3 finite
+ * fields: p < 2^31, exact arithmetic, division by the modular inverse).
+ *   p        odd prime, 3 <= p < 2^31 (checked with a deterministic
+ *            Miller-Rabin test; BG_ENOTPRIME otherwise)
+ *   momenta, pols  device, uint32 [n][d][ld], canonical residues in [0, p)
+ *   out      device, uint32 [npts]: M mod p in [0, p), or 0xFFFFFFFF
+ *   other arguments as for bg_amplitudes_c128.
+ */
+int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p,
+                     const uint32_t* momenta, const uint32_t* pols,
+                     uint32_t* out, uint8_t* status, void* hip_stream);
+
+/* Human-readable text for a return code (static storage). */
+const char* bg_strerror(int code);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int bg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BG_MI355X_H */

@@ -13,6 +13,9 @@ written once:
                     the double-precision complex path of the paper (Sec. 3).
 * ``Rationals``  -- ``fractions.Fraction``, exact; used to arbitrate FP64
                     rounding and to tie the two other fields together.
+* ``GaussianRationals`` -- pairs of Fractions (a + b i), exact; the exact
+                    value of an FP64 complex input (every binary64 number is a
+                    dyadic rational), used to arbitrate complex rounding.
 
 Minkowski products use the mostly-minus metric diag(+1, -1, ..., -1) of
 Sec. 2.3 (the completeness relation is written with the "mostly negative
@@ -165,3 +168,43 @@ def vsub(F, x, y):
 
 def vscale(F, c, x):
     return [F.mul(c, a) for a in x]
+
+
+class GaussianRationals:
+    """Exact complex rationals a + b i as (Fraction, Fraction) pairs."""
+
+    name = "qi"
+    exact = True
+    zero = (Fraction(0), Fraction(0))
+    one = (Fraction(1), Fraction(0))
+
+    def elem(self, x):
+        if isinstance(x, tuple):
+            return (Fraction(x[0]), Fraction(x[1]))
+        z = complex(x)
+        return (Fraction(z.real), Fraction(z.imag))
+
+    def add(self, a, b):
+        return (a[0] + b[0], a[1] + b[1])
+
+    def sub(self, a, b):
+        return (a[0] - b[0], a[1] - b[1])
+
+    def mul(self, a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    def neg(self, a):
+        return (-a[0], -a[1])
+
+    def inv(self, a):
+        n = a[0] * a[0] + a[1] * a[1]
+        if n == 0:
+            raise ZeroDivisionError("inverse of 0 in Q(i)")
+        return (a[0] / n, -a[1] / n)
+
+    def is_zero(self, a) -> bool:
+        return a[0] == 0 and a[1] == 0
+
+    @staticmethod
+    def to_complex(a) -> complex:
+        return complex(float(a[0]), float(a[1]))

@@ -1,0 +1,222 @@
+// C-ABI entry points of libbg_mi355x.so (declared in include/bg.h).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "bg.h"
+#include "bg_generic.h"
+#include "bg_registry.h"
+
+namespace bg {
+
+std::vector<Variant>& registry() {
+  static std::vector<Variant> r;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// primes and Montgomery constants
+// ---------------------------------------------------------------------------
+static uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = (unsigned __int128)r * a % m;
+    a = (unsigned __int128)a * a % m;
+    e >>= 1;
+  }
+  return r;
+}
+
+// Deterministic Miller-Rabin for n < 4,759,123,141 with bases 2, 7, 61
+// (Jaeschke 1993).
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t sp : {2u, 3u, 5u, 7u, 11u, 13u, 61u})
+    if (n % sp == 0) return n == sp;
+  uint32_t dd = n - 1;
+  int r = 0;
+  while ((dd & 1) == 0) { dd >>= 1; ++r; }
+  for (uint32_t base : {2u, 7u, 61u}) {
+    uint64_t x = powmod(base, dd, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r; ++i) {
+      x = (unsigned __int128)x * x % n;
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+static int32_t balanced(uint64_t x, uint32_t p) {
+  x %= p;
+  return x > (p - 1) / 2 ? (int32_t)((int64_t)x - p) : (int32_t)x;
+}
+
+FpConst make_fp_const(uint32_t p) {
+  FpConst k;
+  k.p = (int32_t)p;
+  k.h = (int32_t)((p - 1) / 2);
+  uint32_t inv = p;  // Newton iteration for p^-1 mod 2^32 (p odd)
+  for (int i = 0; i < 5; ++i) inv *= 2u - p * inv;
+  k.pinv = inv;
+  const uint64_t R = (uint64_t(1) << 32) % p;
+  k.c32 = balanced(R, p);
+  k.one = balanced(R, p);
+  k.two = balanced(2 * R, p);
+  k.inv2 = balanced((unsigned __int128)R * ((p + 1) / 2) % p, p);
+  const uint64_t R2 = (unsigned __int128)R * R % p;
+  k.r4 = balanced((unsigned __int128)R2 * R2 % p, p);
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// variant choice
+// ---------------------------------------------------------------------------
+static int preferred_lanes(int field, int N, int d) {
+  if (field == FIELD_FP) return 1;
+  // complex: one lane per point only while the current table is small
+  return (N <= 3 && d <= 4) ? 1 : 4;
+}
+
+const Variant* choose_variant(int field, int n, int d) {
+  const int N = n - 1;
+  const int L = preferred_lanes(field, N, d);
+  const int need = (d + L - 1) / L;
+  const Variant* best = nullptr;
+  for (const Variant& v : registry()) {
+    if (v.generic || v.field != field || v.N != N || v.L != L || v.DL < need) continue;
+    if (!best || v.DL < best->DL) best = &v;
+  }
+  if (best) return best;
+  for (const Variant& v : registry()) {
+    if (!v.generic || v.field != field || v.DL < d) continue;
+    if (!best || v.DL < best->DL) best = &v;
+  }
+  return best;
+}
+
+static size_t generic_bytes_per_point(int field, int N, int dmax) {
+  const size_t e = field == FIELD_FP ? 4 : 16;
+  const int ncur = N * (N + 1) / 2 - 1;
+  const int nprop = std::max(0, N * (N - 1) / 2 - 1);
+  return (size_t)(ncur + N + 1) * dmax * e + (size_t)2 * ncur * e + (size_t)nprop * e;
+}
+
+static int max_lds_per_block() {
+  static std::once_flag once;
+  static int v = 65536;
+  std::call_once(once, [] {
+    int dev = 0, val = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        val > 0)
+      v = val;
+  });
+  return v;
+}
+
+int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
+           void* out, uint8_t* status, const FpConst& fp, hipStream_t stream) {
+  const Variant* v = choose_variant(field, n, d);
+  if (!v) return BG_ENOTIMPL;
+  LaunchArgs a;
+  a.momenta = momenta;
+  a.pols = pols;
+  a.out = out;
+  a.status = status;
+  a.npts = npts;
+  a.ld = ld;
+  a.d = d;
+  a.fp = fp;
+  if (!v->generic) {
+    const int64_t threads = npts * v->L;
+    const int64_t blocks = (threads + v->block - 1) / v->block;
+    if (blocks > 0x7FFFFFFF) return BG_EINVAL;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(v->block), args, 0, stream);
+    return e == hipSuccess ? BG_OK : BG_EHIP;
+  }
+  const int N = n - 1;
+  const size_t per = generic_bytes_per_point(field, N, v->DL);
+  const int maxlds = max_lds_per_block();
+  int P = (int)std::min<size_t>(256, (size_t)maxlds / per);
+  if (P >= 64) P = P / 64 * 64;
+  if (P < 1) return BG_ENOTIMPL;
+  const size_t shmem = per * P;
+  if (shmem > 65536) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    (void)hipFuncSetAttribute(v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  }
+  const int64_t blocks = (npts + P - 1) / P;
+  if (blocks > 0x7FFFFFFF) return BG_EINVAL;
+  int Narg = N;
+  void* args[] = {&a, &Narg};
+  hipError_t e = hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(P), args, shmem, stream);
+  return e == hipSuccess ? BG_OK : BG_EHIP;
+}
+
+static int check_common(int n, int d, int64_t npts, int64_t ld) {
+  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
+  if (npts < 0) return BG_EINVAL;
+  (void)ld;
+  return BG_OK;
+}
+
+static int check_buffers(int64_t npts, int64_t ld, const void* m, const void* e, const void* o) {
+  if (ld < npts || !m || !e || !o) return BG_EINVAL;
+  return BG_OK;
+}
+
+}  // namespace bg
+
+extern "C" {
+
+int bg_amplitudes_c128(int n, int d, int64_t npts, int64_t ld, const double* momenta,
+                       const double* pols, double* out, uint8_t* status, void* hip_stream) {
+  int rc = bg::check_common(n, d, npts, ld);
+  if (rc != BG_OK) return rc;
+  if (npts == 0) return BG_OK;
+  rc = bg::check_buffers(npts, ld, momenta, pols, out);
+  if (rc != BG_OK) return rc;
+  bg::FpConst none;
+  memset(&none, 0, sizeof(none));
+  return bg::launch(bg::FIELD_C128, n, d, npts, ld, momenta, pols, out, status, none,
+                    static_cast<hipStream_t>(hip_stream));
+}
+
+int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
+                     const uint32_t* pols, uint32_t* out, uint8_t* status, void* hip_stream) {
+  int rc = bg::check_common(n, d, npts, ld);
+  if (rc != BG_OK) return rc;
+  if (p < 3 || p >= 0x80000000u || !bg::is_prime_u32(p)) return BG_ENOTPRIME;
+  if (npts == 0) return BG_OK;
+  rc = bg::check_buffers(npts, ld, momenta, pols, out);
+  if (rc != BG_OK) return rc;
+  const bg::FpConst k = bg::make_fp_const(p);
+  return bg::launch(bg::FIELD_FP, n, d, npts, ld, momenta, pols, out, status, k,
+                    static_cast<hipStream_t>(hip_stream));
+}
+
+const char* bg_strerror(int code) {
+  switch (code) {
+    case BG_OK: return "success";
+    case BG_EINVAL: return "invalid argument (null pointer, npts < 0 or ld < npts)";
+    case BG_EDOMAIN: return "n or d outside the supported range";
+    case BG_ENOTPRIME: return "p is not an odd prime below 2^31";
+    case BG_EHIP: return "HIP runtime error or kernel launch failure";
+    case BG_ENOTIMPL: return "no kernel for this (field, n, d)";
+    case BG_ENOMEM: return "request does not fit the memory budget";
+    case BG_EBUSY: return "queue full";
+    default: return "unknown error code";
+  }
+}
+
+int bg_version(void) { return 100; }
+
+}  // extern "C"

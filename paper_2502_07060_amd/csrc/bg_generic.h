@@ -1,0 +1,281 @@
+// Generic Berends-Giele recursion with a runtime number of legs (any
+// 3 <= n <= 14): one point per lane, the point's current table, prefix sums
+// and per-current scalars held in LDS as [slot][lane] columns (conflict-free,
+// each lane touches its own column).  Same algebra as bg_kernel.h; used for
+// multiplicities without a register-resident instantiation.
+#pragma once
+
+#include "bg_kernel.h"
+
+namespace bg {
+
+__host__ __device__ constexpr int range_idx(int N, int i, int j) {
+  return ((j - i) * (2 * N - (j - i) + 1)) / 2 + i;
+}
+
+// LDS slots per point: currents and prefix sums (DMAX elements each), then
+// scalars nc, nDh (one per current), then propagator inverses.
+template <class Fld, int DMAX>
+struct GenericLayout {
+  using E = typename Fld::E;
+  using S = typename Fld::S;
+  static __host__ __device__ int ncur(int N) { return N * (N + 1) / 2 - 1; }
+  static __host__ __device__ int nprop(int N) { return N * (N - 1) / 2 - 1 > 0 ? N * (N - 1) / 2 - 1 : 0; }
+  static __host__ __device__ size_t bytes_per_point(int N) {
+    return (size_t)(ncur(N) + N + 1) * DMAX * sizeof(E) + (size_t)2 * ncur(N) * sizeof(S) +
+           (size_t)nprop(N) * sizeof(S);
+  }
+};
+
+template <class Fld, int DMAX>
+struct GenericRecursion {
+  using E = typename Fld::E;
+  using S = typename Fld::S;
+  using A = typename Fld::A;
+  using Lay = GenericLayout<Fld, DMAX>;
+
+  E* Jb;   // [ncur * DMAX][P]
+  E* Qb;   // [(N + 1) * DMAX][P]
+  S* ncb;  // [ncur][P]
+  S* nDb;  // [ncur][P]
+  S* ivb;  // [nprop][P]
+  int P, t, N;
+
+  __device__ GenericRecursion(char* lds, int P_, int t_, int N_) : P(P_), t(t_), N(N_) {
+    const int nc = Lay::ncur(N);
+    Jb = reinterpret_cast<E*>(lds);
+    Qb = Jb + (size_t)nc * DMAX * P;
+    ncb = reinterpret_cast<S*>(Qb + (size_t)(N + 1) * DMAX * P);
+    nDb = ncb + (size_t)nc * P;
+    ivb = nDb + (size_t)nc * P;
+  }
+  __device__ __forceinline__ E& J(int r, int c) { return Jb[((size_t)r * DMAX + c) * P + t]; }
+  __device__ __forceinline__ E& Q(int l, int c) { return Qb[((size_t)l * DMAX + c) * P + t]; }
+  __device__ __forceinline__ S& nc(int r) { return ncb[(size_t)r * P + t]; }
+  __device__ __forceinline__ S& nDh(int r) { return nDb[(size_t)r * P + t]; }
+  __device__ __forceinline__ S& iv(int r) { return ivb[(size_t)r * P + t]; }
+
+  __device__ void loadJ(int r, E (&x)[DMAX]) {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) x[c] = J(r, c);
+  }
+  __device__ void loadQ(int l, E (&x)[DMAX]) {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) x[c] = Q(l, c);
+  }
+  __device__ void primedP(const Fld& F, int i, int j, E (&P_)[DMAX]) {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) P_[c] = F.esub(Q(j + 1, c), Q(i, c));
+    P_[0] = F.prime0(P_[0]);
+  }
+
+  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad, bool& singular,
+                      S& result) {
+    const int nprop = Lay::nprop(N);
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) Q(0, c) = E{};
+    for (int l = 0; l < N; ++l) {
+      E k[DMAX], e[DMAX];
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) {
+        k[c] = Loader<Fld>::get(a, a.momenta, l, c, q, bad);
+        e[c] = Loader<Fld>::get(a, a.pols, l, c, q, bad);
+        J(range_idx(N, l, l), c) = e[c];
+        Q(l + 1, c) = F.eadd(Q(l, c), k[c]);
+      }
+      k[0] = F.prime0(k[0]);
+      nc(range_idx(N, l, l)) = F.ndot(k, e);
+    }
+    E epsn[DMAX];
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) epsn[c] = Loader<Fld>::get(a, a.pols, N, c, q, bad);
+
+    // propagator inverses
+    if constexpr (Fld::exact) {
+      if (nprop > 0) {
+        // prefix products in iv(), y recomputed on the backward pass
+        bool zero = false;
+        int32_t acc = 0;
+        for (int r = 0; r < nprop; ++r) {
+          const int len = lenof(r), i = leftof(r);
+          E Pp[DMAX], Pu[DMAX];
+          primedP(F, i, i + len - 1, Pp);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+          Pu[0] = F.prime0(Pp[0]);
+          int32_t y = F.ndot(Pp, Pu);
+          if (y == 0) { zero = true; y = F.k.one; }
+          acc = (r == 0) ? y : fp_mul(acc, y, F.k);
+          iv(r) = acc;
+        }
+        int32_t tinv = fp_pow(acc, (uint32_t)(F.k.p - 2), F.k);
+        tinv = fp_mul(tinv, -F.k.two, F.k);
+        for (int r = nprop - 1; r >= 0; --r) {
+          const int len = lenof(r), i = leftof(r);
+          E Pp[DMAX], Pu[DMAX];
+          primedP(F, i, i + len - 1, Pp);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+          Pu[0] = F.prime0(Pp[0]);
+          int32_t y = F.ndot(Pp, Pu);
+          if (y == 0) y = F.k.one;
+          const int32_t pre = r > 0 ? iv(r - 1) : 0;
+          iv(r) = r > 0 ? fp_mul(tinv, pre, F.k) : tinv;
+          tinv = fp_mul(tinv, y, F.k);
+        }
+        singular = zero;
+      }
+    }
+
+    for (int m = 2; m <= N; ++m) {
+      for (int i = 0; i + m - 1 < N; ++i) {
+        const int j = i + m - 1;
+        const bool root = (m == N);
+        E Pp[DMAX];
+        primedP(F, i, j, Pp);
+        A K[DMAX];
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) K[c] = F.azero();
+        S nDsum = F.szero();
+        for (int tt = i; tt < j; ++tt) {
+          const int ia = range_idx(N, i, tt), ib = range_idx(N, tt + 1, j);
+          E JA[DMAX], JB[DMAX], Qt[DMAX];
+          loadJ(ia, JA);
+          loadJ(ib, JB);
+          loadQ(tt + 1, Qt);
+          const S nDm = F.ndot_u(JA, JB);
+          const S nc2 = F.ndot_sub(Pp, JA, nc(ia));
+          const S nc3 = F.ndot_sub(Pp, JB, nc(ib));
+          F.axpy(K, F.sneg(nDm), Qt);
+          F.axpy(K, F.sneg(nc2), JB);
+          F.axpy(K, nc3, JA);
+          F.fold(K);
+          nDsum = Recursion<Fld, 2, DMAX, 1>::accumulate_scalar(F, nDsum, nDm);
+        }
+        const S nDhS = Recursion<Fld, 2, DMAX, 1>::half_scalar(F, nDsum);
+        {
+          E Qi[DMAX], Qj[DMAX];
+          loadQ(i, Qi);
+          loadQ(j + 1, Qj);
+          F.axpy(K, nDhS, Qi);
+          F.axpy(K, nDhS, Qj);
+          F.fold(K);
+        }
+        if (!root) nDh(range_idx(N, i, j)) = nDhS;
+        int cnt = 0;
+        for (int s1 = i; s1 < j - 1; ++s1) {
+          E JA[DMAX];
+          loadJ(range_idx(N, i, s1), JA);
+          for (int tt = s1 + 1; tt < j; ++tt) {
+            E JB[DMAX], JC[DMAX];
+            loadJ(range_idx(N, s1 + 1, tt), JB);
+            loadJ(range_idx(N, tt + 1, j), JC);
+            const S ne = F.ndot_u(JA, JC);
+            F.axpy(K, F.sneg(ne), JB);
+            if (++cnt == 5) { F.fold(K); cnt = 0; }
+          }
+        }
+        F.fold(K);
+        cnt = 0;
+        for (int tt = i + 1; tt < j; ++tt) {
+          E JC[DMAX];
+          loadJ(range_idx(N, tt + 1, j), JC);
+          F.axpy(K, nDh(range_idx(N, i, tt)), JC);
+          if (++cnt == 5) { F.fold(K); cnt = 0; }
+        }
+        F.fold(K);
+        cnt = 0;
+        for (int s1 = i; s1 < j - 1; ++s1) {
+          E JA[DMAX];
+          loadJ(range_idx(N, i, s1), JA);
+          F.axpy(K, nDh(range_idx(N, s1 + 1, j)), JA);
+          if (++cnt == 5) { F.fold(K); cnt = 0; }
+        }
+        if (!root) {
+          S inv2;
+          if constexpr (Fld::exact) {
+            inv2 = iv(range_idx(N, i, j) - N);
+          } else {
+            E Pu[DMAX];
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+            Pu[0] = F.prime0(Pp[0]);
+            const S y = F.ndot(Pp, Pu);
+            inv2 = Recursion<Fld, 2, DMAX, 1>::c_inverse_times(y, -2.0, singular);
+          }
+          const int id = range_idx(N, i, j);
+          E Jn[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            Jn[c] = F.mul(F.finish(K[c]), inv2);
+            J(id, c) = Jn[c];
+          }
+          nc(id) = F.ndot(Pp, Jn);
+        } else {
+          E Kf[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) Kf[c] = F.finish(K[c]);
+          result = F.ndot_u(epsn, Kf);
+        }
+      }
+    }
+  }
+
+  // propagator index r (ranges of length >= 2 in length-major order) -> length, left end
+  __device__ int lenof(int r) const {
+    int len = 2, base = 0;
+    while (r >= base + (N - len + 1)) { base += N - len + 1; ++len; }
+    return len;
+  }
+  __device__ int leftof(int r) const {
+    int len = 2, base = 0;
+    while (r >= base + (N - len + 1)) { base += N - len + 1; ++len; }
+    return r - base;
+  }
+};
+
+template <class Fld, int DMAX>
+__global__ __launch_bounds__(256) void bg_generic_kernel(LaunchArgs a, int N) {
+  extern __shared__ __align__(16) char lds[];
+  const int P = blockDim.x;
+  const int t = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * P + t;
+  const bool valid = q0 < a.npts;
+  const int64_t q = valid ? q0 : a.npts - 1;
+  uint32_t bad = 0;
+  bool singular = false;
+  typename Fld::S res;
+  GenericRecursion<Fld, DMAX> G(lds, P, t, N);
+  if constexpr (Fld::exact) {
+    Fld F(a.fp, 0);
+    G.run(F, a, q, bad, singular, res);
+    if (valid) {
+      uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
+      uint32_t outv = 0xFFFFFFFFu;
+      if (st == PT_OK) {
+        int32_t m = fp_mul(res, a.fp.r4, a.fp);
+        m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
+        outv = fp_to_canonical(m, a.fp);
+      }
+      static_cast<uint32_t*>(a.out)[q] = outv;
+      if (a.status) a.status[q] = st;
+    }
+  } else {
+    Fld F(0);
+    G.run(F, a, q, bad, singular, res);
+    if (valid) {
+      double2 o;
+      if (singular) {
+        o.x = __builtin_nan("");
+        o.y = __builtin_nan("");
+      } else {
+        o.x = -2.0 * res.re;
+        o.y = -2.0 * res.im;
+      }
+      static_cast<double2*>(a.out)[q] = o;
+      if (a.status) a.status[q] = singular ? PT_SINGULAR : PT_OK;
+    }
+  }
+}
+
+}  // namespace bg

@@ -1,0 +1,106 @@
+"""Shared helpers for the parity tests: batch oracle evaluation and the
+complex-path tolerance rule.
+
+Tolerance (complex128).  The bar is relative 1e-11.  Each point also has a
+natural size, size = prod_l |eps_l| * E^(4-n) with E the largest |k_l^0|
+(the amplitude is multilinear in the eps_l and homogeneous of degree 4-n in
+the momenta); FP64 rounding in any evaluation order is a small multiple of
+1e-16 * size.  A point passes when
+    |gpu - oracle| <= 1e-11 * max(|oracle|, 1e-3 * size).
+Points that vanish exactly (tree-level all-plus / one-minus and conjugates
+in d = 4) have |oracle| ~ 1e-16 size and are covered by the size floor.  A
+point that still fails is arbitrated by the exact value of the same binary64
+inputs (Gaussian rationals): the GPU value passes if it is no further from
+the exact amplitude than max(1e-11 |exact|, 4 x the oracle's own error).
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+from oracle import bg as obg
+from oracle import fields
+
+_POOL = None
+
+
+def _workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def pool():
+    global _POOL
+    if _POOL is None:
+        _POOL = mp.get_context("fork").Pool(_workers())
+    return _POOL
+
+
+def _fp_one(args):
+    p, k, e = args
+    F = fields.Fp(p)
+    return obg.amplitude(F, [[int(x) for x in v] for v in k], [[int(x) for x in v] for v in e])
+
+
+def _c_one(args):
+    k, e = args
+    F = fields.Complex128()
+    return obg.amplitude(F, [[complex(x) for x in v] for v in k], [[complex(x) for x in v] for v in e])
+
+
+def _exact_one(args):
+    k, e = args
+    G = fields.GaussianRationals()
+    st, m = obg.amplitude(G, [[G.elem(complex(x)) for x in v] for v in k],
+                          [[G.elem(complex(x)) for x in v] for v in e])
+    return st, (G.to_complex(m) if st == 0 else complex("nan"))
+
+
+def oracle_fp(k, e, p):
+    """k, e: (npts, n, d) integer arrays -> (status array, value array int64)."""
+    jobs = [(p, k[i], e[i]) for i in range(len(k))]
+    res = pool().map(_fp_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
+    st = np.array([r[0] for r in res], np.uint8)
+    val = np.array([r[1] for r in res], np.int64)
+    return st, val
+
+
+def oracle_c(k, e):
+    jobs = [(k[i], e[i]) for i in range(len(k))]
+    res = pool().map(_c_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
+    st = np.array([r[0] for r in res], np.uint8)
+    val = np.array([r[1] for r in res], np.complex128)
+    return st, val
+
+
+def exact_c(k, e):
+    jobs = [(k[i], e[i]) for i in range(len(k))]
+    res = pool().map(_exact_one, jobs, chunksize=1)
+    return np.array([r[1] for r in res], np.complex128)
+
+
+def natural_size(k, e):
+    n = k.shape[1]
+    scale = np.max(np.abs(k[..., 0]), axis=1)
+    return np.prod(np.linalg.norm(e, axis=-1), axis=1) * scale ** (4 - n)
+
+
+def check_c(gpu, ref, k, e, rel=1e-11, floor=1e-3, label=""):
+    """Apply the tolerance rule; returns the number of arbitrated points."""
+    size = natural_size(k, e)
+    err = np.abs(gpu - ref)
+    lim = rel * np.maximum(np.abs(ref), floor * size)
+    bad = np.nonzero(~(err <= lim))[0]
+    if bad.size == 0:
+        return 0
+    assert bad.size <= max(3, len(gpu) // 1000), (
+        f"{label}: {bad.size} of {len(gpu)} points outside tolerance, first {bad[:5]}, "
+        f"err {err[bad[:5]]}, lim {lim[bad[:5]]}")
+    ex = exact_c(k[bad], e[bad])
+    for t, idx in enumerate(bad):
+        e_gpu = abs(gpu[idx] - ex[t])
+        e_orc = abs(ref[idx] - ex[t])
+        assert e_gpu <= max(rel * abs(ex[t]), 4 * e_orc), (
+            f"{label}: point {idx}: gpu {gpu[idx]} oracle {ref[idx]} exact {ex[t]}")
+    return bad.size

@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/bg.h declares, and rejects bad arguments on the host before any
+launch (paper Sec. 3: p < 2^31 prime; n and d within the supported range)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2502_07060_amd import bg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    syms = set()
+    for name in os.listdir(os.path.join(ROOT, "include")):
+        if name.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", name)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            syms |= set(re.findall(r"\b(bg_[a-z0-9_]+)\s*\(", text))
+    return syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = bg.lib()
+    syms = declared_symbols()
+    assert {"bg_amplitudes_c128", "bg_amplitudes_fp", "bg_strerror", "bg_version"} <= syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(bg._SIGNATURES) >= syms
+
+
+def test_version_and_strerror():
+    assert bg.bg_version() >= 100
+    for code in range(-7, 1):
+        assert bg.strerror(code) != "unknown error code"
+    assert bg.strerror(-99) == "unknown error code"
+
+
+NULL = ctypes.c_void_p(0)
+DUMMY = ctypes.c_void_p(0x1000)   # never dereferenced: every case below fails validation first
+
+
+def call_fp(n=8, d=6, npts=10, ld=10, p=2147483629, m=DUMMY, e=DUMMY, o=DUMMY):
+    return bg.lib().bg_amplitudes_fp(n, d, npts, ld, ctypes.c_uint32(p), m, e, o, NULL, NULL)
+
+
+def call_c(n=8, d=4, npts=10, ld=10, m=DUMMY, e=DUMMY, o=DUMMY):
+    return bg.lib().bg_amplitudes_c128(n, d, npts, ld, m, e, o, NULL, NULL)
+
+
+@pytest.mark.parametrize("n", [-1, 0, 1, 2, 15, 100])
+def test_bad_multiplicity(n):
+    assert call_fp(n=n) == bg.BG_EDOMAIN
+    assert call_c(n=n) == bg.BG_EDOMAIN
+
+
+@pytest.mark.parametrize("d", [0, -3, 11, 64])
+def test_bad_dimension(d):
+    assert call_fp(d=d) == bg.BG_EDOMAIN
+    assert call_c(d=d) == bg.BG_EDOMAIN
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 4, 9, 2147483631, 2147483648, 4294967291, 2147483649])
+def test_bad_prime(p):
+    assert call_fp(p=p) == bg.BG_ENOTPRIME
+
+
+def test_null_pointers_and_ld():
+    assert call_fp(m=NULL) == bg.BG_EINVAL
+    assert call_fp(e=NULL) == bg.BG_EINVAL
+    assert call_fp(o=NULL) == bg.BG_EINVAL
+    assert call_fp(ld=9) == bg.BG_EINVAL
+    assert call_fp(npts=-1) == bg.BG_EINVAL
+    assert call_c(m=NULL) == bg.BG_EINVAL
+    assert call_c(ld=3) == bg.BG_EINVAL
+
+
+def test_zero_points_is_a_noop():
+    assert call_fp(npts=0, ld=0, m=NULL, e=NULL, o=NULL) == bg.BG_OK
+    assert call_c(npts=0, ld=0, m=NULL, e=NULL, o=NULL) == bg.BG_OK
+
+
+def test_primality_matches_oracle():
+    from oracle.fields import is_prime
+    import random
+    rng = random.Random(1)
+    cands = [rng.randrange(3, 2**31) | 1 for _ in range(300)] + [2147483629, 2147483647, 10007, 3, 5]
+    for p in cands:
+        rc = call_fp(p=p, npts=0, ld=0)
+        assert (rc == bg.BG_OK) == is_prime(p), p

@@ -65,3 +65,19 @@ def test_mdot_is_bilinear_not_sesquilinear():
     x = [1j, 2.0, 0.0, 1.0]
     # x.x = (i)^2 - 4 - 0 - 1 = -6 (no conjugation)
     assert fields.mdot(C, x, x) == -6
+
+
+def test_gaussian_rationals_match_complex_arithmetic():
+    G = fields.GaussianRationals()
+    rng = random.Random(5)
+    for _ in range(200):
+        a = complex(rng.randint(-50, 50), rng.randint(-50, 50))
+        b = complex(rng.randint(-50, 50), rng.randint(-50, 50))
+        ga, gb = G.elem(a), G.elem(b)
+        assert G.to_complex(G.mul(ga, gb)) == a * b          # small integers: exact in FP64
+        assert G.to_complex(G.add(ga, gb)) == a + b
+        if b != 0:
+            q = G.mul(ga, G.inv(gb))
+            assert G.mul(q, gb) == ga                          # exact inverse
+    x = G.elem(0.1 + 0.3j)                                     # exact dyadic value of the binary64 input
+    assert x[0] == Fraction(0.1) and x[1] == Fraction(0.3)
