@@ -208,3 +208,51 @@ class GaussianRationals:
     @staticmethod
     def to_complex(a) -> complex:
         return complex(float(a[0]), float(a[1]))
+
+
+class RunningError:
+    """Complex binary64 values carried with a first-order rounding-error bound.
+
+    Elements are (v, e): v the binary64 result of the operation exactly as
+    ``Complex128`` computes it, e a bound, in units of the unit roundoff
+    u = 2^-53, on |v - exact| accumulated to first order (running error
+    analysis, Wilkinson 1963):
+        e(a +- b) = e(a) + e(b) + |a +- b|
+        e(a * b)  = |a| e(b) + |b| e(a) + 4 |a b|     (complex product, one rounding per part)
+        e(1 / a)  = e(a) / |a|^2 + 4 |1 / a|
+    Used only to size the tolerance floor of complex parity checks: two
+    evaluations of the same amplitude in different orders differ by at most
+    about u (e_1 + e_2).
+    """
+
+    name = "c128_err"
+    exact = False
+    zero = (0j, 0.0)
+    one = (1 + 0j, 0.0)
+
+    def elem(self, x):
+        return (complex(x), 0.0)
+
+    def add(self, a, b):
+        v = a[0] + b[0]
+        return (v, a[1] + b[1] + abs(v))
+
+    def sub(self, a, b):
+        v = a[0] - b[0]
+        return (v, a[1] + b[1] + abs(v))
+
+    def mul(self, a, b):
+        v = a[0] * b[0]
+        return (v, abs(a[0]) * b[1] + abs(b[0]) * a[1] + 4 * abs(v))
+
+    def neg(self, a):
+        return (-a[0], a[1])
+
+    def inv(self, a):
+        if a[0] == 0:
+            raise ZeroDivisionError("inverse of 0 in C")
+        v = 1 / a[0]
+        return (v, a[1] / abs(a[0]) ** 2 + 4 * abs(v))
+
+    def is_zero(self, a) -> bool:
+        return a[0] == 0

@@ -104,7 +104,7 @@ static size_t generic_bytes_per_point(int field, int N, int dmax) {
   const size_t e = field == FIELD_FP ? 4 : 16;
   const int ncur = N * (N + 1) / 2 - 1;
   const int nprop = std::max(0, N * (N - 1) / 2 - 1);
-  return (size_t)(ncur + N + 1) * dmax * e + (size_t)2 * ncur * e + (size_t)nprop * e;
+  return (size_t)(ncur + 2 * N + 1) * dmax * e + (size_t)2 * ncur * e + (size_t)nprop * e;
 }
 
 static int max_lds_per_block() {

@@ -1,8 +1,8 @@
 // Generic Berends-Giele recursion with a runtime number of legs (any
-// 3 <= n <= 14): one point per lane, the point's current table, prefix sums
-// and per-current scalars held in LDS as [slot][lane] columns (conflict-free,
-// each lane touches its own column).  Same algebra as bg_kernel.h; used for
-// multiplicities without a register-resident instantiation.
+// 3 <= n <= 14): one point per lane, the point's current table, momenta and
+// per-current scalars held in LDS as [slot][lane] columns (conflict-free,
+// each lane touches its own column).  Same algebra and visiting order as
+// bg_kernel.h; used for shapes without a register-resident instantiation.
 #pragma once
 
 #include "bg_kernel.h"
@@ -13,8 +13,11 @@ __host__ __device__ constexpr int range_idx(int N, int i, int j) {
   return ((j - i) * (2 * N - (j - i) + 1)) / 2 + i;
 }
 
-// LDS slots per point: currents and prefix sums (DMAX elements each), then
-// scalars nc, nDh (one per current), then propagator inverses.
+// LDS slots per point: currents (DMAX elements each), then N + 1 vector slots
+// of momenta (F_p: prefix sums Q_0..Q_N; complex: primed k'_0..k'_{N-1} and,
+// in the last slot, nothing), then N column slots (complex: P'_{i..j} for the
+// current right end j), then scalars nc (F_p) and nDh, then propagator
+// inverses (F_p).
 template <class Fld, int DMAX>
 struct GenericLayout {
   using E = typename Fld::E;
@@ -22,7 +25,7 @@ struct GenericLayout {
   static __host__ __device__ int ncur(int N) { return N * (N + 1) / 2 - 1; }
   static __host__ __device__ int nprop(int N) { return N * (N - 1) / 2 - 1 > 0 ? N * (N - 1) / 2 - 1 : 0; }
   static __host__ __device__ size_t bytes_per_point(int N) {
-    return (size_t)(ncur(N) + N + 1) * DMAX * sizeof(E) + (size_t)2 * ncur(N) * sizeof(S) +
+    return (size_t)(ncur(N) + 2 * N + 1) * DMAX * sizeof(E) + (size_t)2 * ncur(N) * sizeof(S) +
            (size_t)nprop(N) * sizeof(S);
   }
 };
@@ -33,9 +36,12 @@ struct GenericRecursion {
   using S = typename Fld::S;
   using A = typename Fld::A;
   using Lay = GenericLayout<Fld, DMAX>;
+  using Rec = Recursion<Fld, 2, DMAX, 1>;  // scalar helpers
+  static constexpr bool kFp = Fld::exact;
 
   E* Jb;   // [ncur * DMAX][P]
-  E* Qb;   // [(N + 1) * DMAX][P]
+  E* Qb;   // [(N + 1) * DMAX][P]   F_p: Q_l; complex: k'_l
+  E* Cb;   // [N * DMAX][P]         complex: column P'_{i..j}
   S* ncb;  // [ncur][P]
   S* nDb;  // [ncur][P]
   S* ivb;  // [nprop][P]
@@ -45,12 +51,14 @@ struct GenericRecursion {
     const int nc = Lay::ncur(N);
     Jb = reinterpret_cast<E*>(lds);
     Qb = Jb + (size_t)nc * DMAX * P;
-    ncb = reinterpret_cast<S*>(Qb + (size_t)(N + 1) * DMAX * P);
+    Cb = Qb + (size_t)(N + 1) * DMAX * P;
+    ncb = reinterpret_cast<S*>(Cb + (size_t)N * DMAX * P);
     nDb = ncb + (size_t)nc * P;
     ivb = nDb + (size_t)nc * P;
   }
   __device__ __forceinline__ E& J(int r, int c) { return Jb[((size_t)r * DMAX + c) * P + t]; }
   __device__ __forceinline__ E& Q(int l, int c) { return Qb[((size_t)l * DMAX + c) * P + t]; }
+  __device__ __forceinline__ E& Col(int i, int c) { return Cb[((size_t)i * DMAX + c) * P + t]; }
   __device__ __forceinline__ S& nc(int r) { return ncb[(size_t)r * P + t]; }
   __device__ __forceinline__ S& nDh(int r) { return nDb[(size_t)r * P + t]; }
   __device__ __forceinline__ S& iv(int r) { return ivb[(size_t)r * P + t]; }
@@ -63,6 +71,10 @@ struct GenericRecursion {
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) x[c] = Q(l, c);
   }
+  __device__ void loadCol(int i, E (&x)[DMAX]) {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) x[c] = Col(i, c);
+  }
   __device__ void primedP(const Fld& F, int i, int j, E (&P_)[DMAX]) {
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) P_[c] = F.esub(Q(j + 1, c), Q(i, c));
@@ -72,8 +84,10 @@ struct GenericRecursion {
   __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad, bool& singular,
                       S& result) {
     const int nprop = Lay::nprop(N);
+    if constexpr (kFp) {
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) Q(0, c) = E{};
+      for (int c = 0; c < DMAX; ++c) Q(0, c) = E{};
+    }
     for (int l = 0; l < N; ++l) {
       E k[DMAX], e[DMAX];
 #pragma unroll
@@ -81,29 +95,29 @@ struct GenericRecursion {
         k[c] = Loader<Fld>::get(a, a.momenta, l, c, q, bad);
         e[c] = Loader<Fld>::get(a, a.pols, l, c, q, bad);
         J(range_idx(N, l, l), c) = e[c];
-        Q(l + 1, c) = F.eadd(Q(l, c), k[c]);
       }
       k[0] = F.prime0(k[0]);
-      nc(range_idx(N, l, l)) = F.ndot(k, e);
+      if constexpr (kFp) {
+        nc(range_idx(N, l, l)) = F.ndot(k, e);
+        k[0] = F.prime0(k[0]);
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) Q(l + 1, c) = F.eadd(Q(l, c), k[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) Q(l, c) = k[c];
+      }
     }
     E epsn[DMAX];
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) epsn[c] = Loader<Fld>::get(a, a.pols, N, c, q, bad);
 
-    // propagator inverses
-    if constexpr (Fld::exact) {
+    // F_p propagator inverses: prefix products in iv(), y recomputed backwards
+    if constexpr (kFp) {
       if (nprop > 0) {
-        // prefix products in iv(), y recomputed on the backward pass
         bool zero = false;
         int32_t acc = 0;
         for (int r = 0; r < nprop; ++r) {
-          const int len = lenof(r), i = leftof(r);
-          E Pp[DMAX], Pu[DMAX];
-          primedP(F, i, i + len - 1, Pp);
-#pragma unroll
-          for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
-          Pu[0] = F.prime0(Pp[0]);
-          int32_t y = F.ndot(Pp, Pu);
+          int32_t y = yprop(F, r);
           if (y == 0) { zero = true; y = F.k.one; }
           acc = (r == 0) ? y : fp_mul(acc, y, F.k);
           iv(r) = acc;
@@ -111,13 +125,7 @@ struct GenericRecursion {
         int32_t tinv = fp_pow(acc, (uint32_t)(F.k.p - 2), F.k);
         tinv = fp_mul(tinv, -F.k.two, F.k);
         for (int r = nprop - 1; r >= 0; --r) {
-          const int len = lenof(r), i = leftof(r);
-          E Pp[DMAX], Pu[DMAX];
-          primedP(F, i, i + len - 1, Pp);
-#pragma unroll
-          for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
-          Pu[0] = F.prime0(Pp[0]);
-          int32_t y = F.ndot(Pp, Pu);
+          int32_t y = yprop(F, r);
           if (y == 0) y = F.k.one;
           const int32_t pre = r > 0 ? iv(r - 1) : 0;
           iv(r) = r > 0 ? fp_mul(tinv, pre, F.k) : tinv;
@@ -125,35 +133,64 @@ struct GenericRecursion {
         }
         singular = zero;
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) Col(0, c) = Q(0, c);
     }
 
-    for (int m = 2; m <= N; ++m) {
-      for (int i = 0; i + m - 1 < N; ++i) {
-        const int j = i + m - 1;
-        const bool root = (m == N);
+    for (int j = 1; j < N; ++j) {
+      if constexpr (!kFp) {
+        for (int i = 0; i < j; ++i) {
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) Col(i, c) = F.eadd(Col(i, c), Q(j, c));
+        }
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) Col(j, c) = Q(j, c);
+      }
+      for (int i = j - 1; i >= 0; --i) {
+        const bool root = (i == 0 && j == N - 1);
         E Pp[DMAX];
-        primedP(F, i, j, Pp);
+        if constexpr (kFp) primedP(F, i, j, Pp);
+        else loadCol(i, Pp);
         A K[DMAX];
 #pragma unroll
         for (int c = 0; c < DMAX; ++c) K[c] = F.azero();
         S nDsum = F.szero();
+        [[maybe_unused]] E PA[DMAX];
         for (int tt = i; tt < j; ++tt) {
           const int ia = range_idx(N, i, tt), ib = range_idx(N, tt + 1, j);
-          E JA[DMAX], JB[DMAX], Qt[DMAX];
+          E JA[DMAX], JB[DMAX];
           loadJ(ia, JA);
           loadJ(ib, JB);
-          loadQ(tt + 1, Qt);
           const S nDm = F.ndot_u(JA, JB);
-          const S nc2 = F.ndot_sub(Pp, JA, nc(ia));
-          const S nc3 = F.ndot_sub(Pp, JB, nc(ib));
-          F.axpy(K, F.sneg(nDm), Qt);
-          F.axpy(K, F.sneg(nc2), JB);
-          F.axpy(K, nc3, JA);
-          F.fold(K);
-          nDsum = Recursion<Fld, 2, DMAX, 1>::accumulate_scalar(F, nDsum, nDm);
+          if constexpr (kFp) {
+            E Qt[DMAX];
+            loadQ(tt + 1, Qt);
+            const S nc2 = F.ndot_sub(Pp, JA, nc(ia));
+            const S nc3 = F.ndot_sub(Pp, JB, nc(ib));
+            F.axpy(K, F.sneg(nDm), Qt);
+            F.axpy(K, F.sneg(nc2), JB);
+            F.axpy(K, nc3, JA);
+            F.fold(K);
+          } else {
+            E kt[DMAX], PB[DMAX], v[DMAX];
+            loadQ(tt, kt);
+            loadCol(tt + 1, PB);
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) PA[c] = (tt == i) ? kt[c] : F.eadd(PA[c], kt[c]);
+            const S n2 = F.ndot(PB, JA);
+            const S n3 = F.ndot(PA, JB);
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) v[c] = F.esub(PA[c], PB[c]);
+            v[0] = F.prime0(v[0]);
+            F.axpy(K, cplx{-0.5 * nDm.re, -0.5 * nDm.im}, v);
+            F.axpy(K, F.sneg(n2), JB);
+            F.axpy(K, n3, JA);
+          }
+          nDsum = Rec::accumulate_scalar(F, nDsum, nDm);
         }
-        const S nDhS = Recursion<Fld, 2, DMAX, 1>::half_scalar(F, nDsum);
-        {
+        const S nDhS = Rec::half_scalar(F, nDsum);
+        if constexpr (kFp) {
           E Qi[DMAX], Qj[DMAX];
           loadQ(i, Qi);
           loadQ(j + 1, Qj);
@@ -193,7 +230,7 @@ struct GenericRecursion {
         }
         if (!root) {
           S inv2;
-          if constexpr (Fld::exact) {
+          if constexpr (kFp) {
             inv2 = iv(range_idx(N, i, j) - N);
           } else {
             E Pu[DMAX];
@@ -201,7 +238,7 @@ struct GenericRecursion {
             for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
             Pu[0] = F.prime0(Pp[0]);
             const S y = F.ndot(Pp, Pu);
-            inv2 = Recursion<Fld, 2, DMAX, 1>::c_inverse_times(y, -2.0, singular);
+            inv2 = Rec::c_inverse_times(y, -2.0, singular);
           }
           const int id = range_idx(N, i, j);
           E Jn[DMAX];
@@ -210,7 +247,7 @@ struct GenericRecursion {
             Jn[c] = F.mul(F.finish(K[c]), inv2);
             J(id, c) = Jn[c];
           }
-          nc(id) = F.ndot(Pp, Jn);
+          if constexpr (kFp) nc(id) = F.ndot(Pp, Jn);
         } else {
           E Kf[DMAX];
 #pragma unroll
@@ -219,6 +256,17 @@ struct GenericRecursion {
         }
       }
     }
+  }
+
+  // -P_S^2 for propagator index r (F_p)
+  __device__ int32_t yprop(const Fld& F, int r) {
+    const int len = lenof(r), i = leftof(r);
+    E Pp[DMAX], Pu[DMAX];
+    primedP(F, i, i + len - 1, Pp);
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+    Pu[0] = F.prime0(Pp[0]);
+    return F.ndot(Pp, Pu);
   }
 
   // propagator index r (ranges of length >= 2 in length-major order) -> length, left end

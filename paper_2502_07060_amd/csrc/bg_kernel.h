@@ -6,22 +6,29 @@
 // What each point computes (identities exact in any field, valid for any
 // inputs; no on-shell or transversality assumption):
 //
-//   Q_l = k_1 + ... + k_l  (prefix sums),  P_S = Q_{j+1} - Q_i  for S = [i..j]
-//   c(X)  = P_X . J_X                     (one scalar per current)
 //   D(X)  = sum over splits A|B of X of J_A . J_B,  Dh = D / 2
 //
 // and, with K'(S) = K(S) / 2 (K the bracket of the paper's recursion once the
 // factors of i are cancelled),
 //
-//   K'(S) = sum_{A|B} [ (J_A.J_B) Q_{a+1} + (P_S.J_A - c(A)) J_B - (P_S.J_B - c(B)) J_A ]
-//         - Dh(S) (Q_i + Q_{j+1})
+//   K'(S) = sum_{A|B} [ (1/2)(J_A.J_B)(P_A - P_B) + (P_B.J_A) J_B - (P_A.J_B) J_A ]
 //         + sum_{A|B|C} (J_A.J_C) J_B
 //         - sum_t Dh([i..t]) J([t+1..j]) - sum_s Dh([s+1..j]) J([i..s])
 //
-// where a is the last leg of A.  The first line is the three-gluon vertex
-// (P_A - P_B = 2 Q_{a+1} - Q_i - Q_{j+1}, P_B = P_S - P_A); the last two lines
-// are the four-gluon vertex with the two adjacent-pair dot products summed
-// into Dh.  Then J(S) = 2 K'(S) / P_S^2 and M = 2 eps_n . K'([1..N]).
+// The first line is the three-gluon vertex; the last two are the four-gluon
+// vertex with its two adjacent-pair dot products summed into Dh.  Then
+// J(S) = 2 K'(S) / P_S^2 and M = 2 eps_n . K'([1..N]).  Ranges are visited
+// column by column (right end j ascending, left end i descending), so every
+// range a split reads is already final.
+//
+// Sub-range momenta.  Over F_p every identity is exact, so with prefix sums
+// Q_l = k_1 + ... + k_l, P_S = Q_{j+1} - Q_i, c(X) = P_X . J_X one has
+// P_B.J_A = P_S.J_A - c(A), P_A.J_B = P_S.J_B - c(B) and
+// P_A - P_B = 2 Q_{a+1} - Q_i - Q_{j+1}: no vector of momenta is formed per
+// split.  Over C the momenta are summed left to right exactly as the
+// definition P_{i,j} = k_i + ... + k_j reads (the column P_{i..j} for the
+// current j, and P_A grown along the split loop), which keeps the rounding of
+// small sub-range momenta independent of the size of the partial sums.
 #pragma once
 
 #include "bg_common.h"
@@ -119,16 +126,25 @@ struct Recursion {
 
   __device__ static void run(const Fld& F, const LaunchArgs& a, int64_t q, int s, uint32_t& bad,
                              bool& singular, S& result) {
+    constexpr bool kFp = Fld::exact;
     E J[NCUR][DL];
-    E Q[N + 1][DL];
-    S nc[NCUR];            // -(P_X . J_X)
-    S nDh[NCUR > 0 ? NCUR : 1];  // -Dh(X) for |X| >= 2 (indexed by range index)
+    S nDh[NCUR];                 // -Dh(X) for |X| >= 2 (indexed by range index)
     E epsn[DL];
+    // F_p: prefix sums Q_l and nc(X) = -(P_X . J_X); exact, so P_S = Q_{j+1} - Q_i.
+    E Q[kFp ? N + 1 : 1][DL];
+    S nc[kFp ? NCUR : 1];
+    // complex: primed momenta k'_l and the primed column P'_{i..j} for the
+    // current right end j, both built by left-to-right sums exactly as the
+    // definition of P_{i,j} reads (no differences of large partial sums).
+    E kp[kFp ? 1 : N][DL];
+    E col[kFp ? 1 : N][DL];
     const int mu0 = s * DL;
 
-    // ---- a1: loads; a2: prefix sums Q_l --------------------------------------
+    // ---- a1: loads; a2: sub-range momenta ----------------------------------
+    if constexpr (kFp) {
 #pragma unroll
-    for (int c = 0; c < DL; ++c) Q[0][c] = E{};
+      for (int c = 0; c < DL; ++c) Q[0][c] = E{};
+    }
     static_for<0, N>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       E k[DL];
@@ -136,24 +152,22 @@ struct Recursion {
       for (int c = 0; c < DL; ++c) {
         k[c] = Loader<Fld>::get(a, a.momenta, l, mu0 + c, q, bad);
         J[R::idx(l, l)][c] = Loader<Fld>::get(a, a.pols, l, mu0 + c, q, bad);
-        Q[l + 1][c] = F.eadd(Q[l][c], k[c]);
       }
-      E kp[DL];
+      k[0] = F.prime0(k[0]);
+      if constexpr (kFp) {
+        nc[R::idx(l, l)] = F.ndot(k, J[R::idx(l, l)]);
+        k[0] = F.prime0(k[0]);
 #pragma unroll
-      for (int c = 0; c < DL; ++c) kp[c] = (c == 0) ? F.prime0(k[0]) : k[c];
-      nc[R::idx(l, l)] = F.ndot(kp, J[R::idx(l, l)]);
+        for (int c = 0; c < DL; ++c) Q[l + 1][c] = F.eadd(Q[l][c], k[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < DL; ++c) kp[l][c] = k[c];
+      }
     });
 #pragma unroll
     for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::get(a, a.pols, N, mu0 + c, q, bad);
 
-    // ---- a3/a4: propagator denominators and inverses --------------------------
-    auto unprime = [&](const E (&Pp)[DL], E (&P)[DL]) {
-#pragma unroll
-      for (int c = 0; c < DL; ++c) P[c] = Pp[c];
-      P[0] = F.prime0(Pp[0]);
-    };
-
-    constexpr bool kFp = Fld::exact;
+    // ---- a3/a4 (F_p): all propagator denominators, one batched inversion -----
     [[maybe_unused]] Inverses<Fld, NP> invs;
     if constexpr (kFp) {
       int32_t y[NP > 0 ? NP : 1];  // y(S) = -P_S^2
@@ -164,45 +178,82 @@ struct Recursion {
           constexpr int j = i + m - 1;
           E Pp[DL], P[DL];
           primedP<i, j>(F, Q, Pp);
-          unprime(Pp, P);
+          unprime(F, Pp, P);
           y[R::pidx(i, j)] = F.ndot(Pp, P);
         });
       });
       singular = invs.compute(F, y);
+    } else {
+#pragma unroll
+      for (int c = 0; c < DL; ++c) col[0][c] = kp[0][c];
     }
 
-    // ---- a5: the recursion by sub-range length ---------------------------------
-    static_for<2, N + 1>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      static_for<0, N - m + 1>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        constexpr int j = i + m - 1;
-        constexpr bool root = (m == N);
+    // ---- a5: the recursion, column by column (right end j), each column from
+    // the shortest range up; every range it reads is already final.
+    static_for<1, N>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if constexpr (!kFp) {
+        // column j: P'_{i..j} = P'_{i..j-1} + k'_j
+        static_for<0, j>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+#pragma unroll
+          for (int c = 0; c < DL; ++c) col[i][c] = F.eadd(col[i][c], kp[j][c]);
+        });
+#pragma unroll
+        for (int c = 0; c < DL; ++c) col[j][c] = kp[j][c];
+      }
+      static_for<0, j>([&](auto ic) {
+        constexpr int i = j - 1 - decltype(ic)::value;
+        constexpr bool root = (i == 0 && j == N - 1);
         E Pp[DL];
-        primedP<i, j>(F, Q, Pp);
+        if constexpr (kFp) {
+          primedP<i, j>(F, Q, Pp);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DL; ++c) Pp[c] = col[i][c];
+        }
         A K[DL];
 #pragma unroll
         for (int c = 0; c < DL; ++c) K[c] = F.azero();
 
         // three-gluon vertex, A = [i..t], B = [t+1..j]
         S nDsum = F.szero();
+        [[maybe_unused]] E PA[DL];
         static_for<i, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
           constexpr int ia = R::idx(i, t), ib = R::idx(t + 1, j);
           const S nDm = F.ndot_u(J[ia], J[ib]);            // -(J_A.J_B)
-          const S nc2 = F.ndot_sub(Pp, J[ia], nc[ia]);     // -(P_S.J_A) + c(A) = -(P_B.J_A)
-          const S nc3 = F.ndot_sub(Pp, J[ib], nc[ib]);     // -(P_A.J_B)
-          F.axpy(K, F.sneg(nDm), Q[t + 1]);
-          F.axpy(K, F.sneg(nc2), J[ib]);
-          F.axpy(K, nc3, J[ia]);
-          F.fold(K);
+          if constexpr (kFp) {
+            // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
+            // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
+            const S nc2 = F.ndot_sub(Pp, J[ia], nc[ia]);   // -(P_B.J_A)
+            const S nc3 = F.ndot_sub(Pp, J[ib], nc[ib]);   // -(P_A.J_B)
+            F.axpy(K, F.sneg(nDm), Q[t + 1]);
+            F.axpy(K, F.sneg(nc2), J[ib]);
+            F.axpy(K, nc3, J[ia]);
+            F.fold(K);
+          } else {
+#pragma unroll
+            for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? kp[i][c] : F.eadd(PA[c], kp[t][c]);
+            const S n2 = F.ndot(col[t + 1], J[ia]);        // -(P_B.J_A)
+            const S n3 = F.ndot(PA, J[ib]);                // -(P_A.J_B)
+            E v[DL];
+#pragma unroll
+            for (int c = 0; c < DL; ++c) v[c] = F.esub(PA[c], col[t + 1][c]);
+            v[0] = F.prime0(v[0]);                         // P_A - P_B
+            F.axpy(K, cplx{-0.5 * nDm.re, -0.5 * nDm.im}, v);
+            F.axpy(K, F.sneg(n2), J[ib]);
+            F.axpy(K, n3, J[ia]);
+          }
           nDsum = accumulate_scalar(F, nDsum, nDm);
         });
-        // -Dh(S) (Q_i + Q_{j+1})
         const S nDhS = half_scalar(F, nDsum);
-        F.axpy(K, nDhS, Q[i]);
-        F.axpy(K, nDhS, Q[j + 1]);
-        F.fold(K);
+        if constexpr (kFp) {
+          // -Dh(S) (Q_i + Q_{j+1})
+          F.axpy(K, nDhS, Q[i]);
+          F.axpy(K, nDhS, Q[j + 1]);
+          F.fold(K);
+        }
         if constexpr (!root) nDh[R::idx(i, j)] = nDhS;
 
         // four-gluon vertex: sum (J_A.J_C) J_B, then the Dh terms
@@ -230,22 +281,22 @@ struct Recursion {
         });
 
         if constexpr (!root) {
-          // J(S) = K' * 2/P_S^2 ; nc(S) = -(P_S . J(S))
+          // J(S) = K' * 2/P_S^2
           S inv2;
           if constexpr (kFp) {
             inv2 = invs.get(R::pidx(i, j));
           } else {
             E P[DL];
-            unprime(Pp, P);
+            unprime(F, Pp, P);
             const S y = F.ndot(Pp, P);  // -P^2
             inv2 = c_inverse_times(y, -2.0, singular);
           }
           constexpr int id = R::idx(i, j);
 #pragma unroll
           for (int c = 0; c < DL; ++c) J[id][c] = F.mul(F.finish(K[c]), inv2);
-          nc[id] = F.ndot(Pp, J[id]);
+          if constexpr (kFp) nc[id] = F.ndot(Pp, J[id]);
         } else {
-          // a6: M = 2 eps_n . K'  (returned negated-and-halved: -(eps_n . K'))
+          // a6: returns -(eps_n . K'); the amplitude is M = 2 eps_n . K'
           E Kf[DL];
 #pragma unroll
           for (int c = 0; c < DL; ++c) Kf[c] = F.finish(K[c]);
@@ -255,7 +306,13 @@ struct Recursion {
     });
   }
 
-  // primed P_S = Q_{j+1} - Q_i with the time slot negated
+  __device__ static __forceinline__ void unprime(const Fld& F, const E (&Pp)[DL], E (&P)[DL]) {
+#pragma unroll
+    for (int c = 0; c < DL; ++c) P[c] = Pp[c];
+    P[0] = F.prime0(Pp[0]);
+  }
+
+  // primed P_S = Q_{j+1} - Q_i with the time slot negated (F_p)
   template <int i, int j>
   __device__ static __forceinline__ void primedP(const Fld& F, const E (&Q)[N + 1][DL], E (&P)[DL]) {
 #pragma unroll

@@ -1,17 +1,18 @@
 """Shared helpers for the parity tests: batch oracle evaluation and the
 complex-path tolerance rule.
 
-Tolerance (complex128).  The bar is relative 1e-11.  Each point also has a
-natural size, size = prod_l |eps_l| * E^(4-n) with E the largest |k_l^0|
-(the amplitude is multilinear in the eps_l and homogeneous of degree 4-n in
-the momenta); FP64 rounding in any evaluation order is a small multiple of
-1e-16 * size.  A point passes when
-    |gpu - oracle| <= 1e-11 * max(|oracle|, 1e-3 * size).
-Points that vanish exactly (tree-level all-plus / one-minus and conjugates
-in d = 4) have |oracle| ~ 1e-16 size and are covered by the size floor.  A
-point that still fails is arbitrated by the exact value of the same binary64
-inputs (Gaussian rationals): the GPU value passes if it is no further from
-the exact amplitude than max(1e-11 |exact|, 4 x the oracle's own error).
+Tolerance (complex128).  The bar is relative 1e-11:
+    |gpu - oracle| <= 1e-11 |oracle|.
+Where FP64 itself cannot deliver that (amplitudes that vanish exactly, such
+as tree-level all-plus / one-minus in d = 4, or ill-conditioned points), the
+floor is the oracle's own first-order rounding-error bound u * e(M)
+(oracle.fields.RunningError, u = 2^-53): a point also passes when
+    |gpu - oracle| <= 1e-11 |oracle| + 2 u e(M),
+i.e. the GPU value lies within the worst-case rounding of the oracle's own
+evaluation order.  A point that still fails is arbitrated by the exact value
+of the same binary64 inputs (Gaussian rationals): it passes only if the GPU
+value is no further from the exact amplitude than
+max(1e-11 |exact|, 4 x the oracle's own error).
 """
 from __future__ import annotations
 
@@ -74,6 +75,20 @@ def oracle_c(k, e):
     return st, val
 
 
+def _err_one(args):
+    k, e = args
+    R = fields.RunningError()
+    st, m = obg.amplitude(R, [[R.elem(x) for x in v] for v in k], [[R.elem(x) for x in v] for v in e])
+    return m[1] if st == 0 else float("inf")
+
+
+def error_bound_c(k, e):
+    """u * e(M): the oracle's running rounding-error bound per point."""
+    jobs = [(k[i], e[i]) for i in range(len(k))]
+    res = pool().map(_err_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
+    return np.array(res) * 2.0 ** -53
+
+
 def exact_c(k, e):
     jobs = [(k[i], e[i]) for i in range(len(k))]
     res = pool().map(_exact_one, jobs, chunksize=1)
@@ -86,21 +101,24 @@ def natural_size(k, e):
     return np.prod(np.linalg.norm(e, axis=-1), axis=1) * scale ** (4 - n)
 
 
-def check_c(gpu, ref, k, e, rel=1e-11, floor=1e-3, label=""):
-    """Apply the tolerance rule; returns the number of arbitrated points."""
-    size = natural_size(k, e)
+def check_c(gpu, ref, k, e, rel=1e-11, label=""):
+    """Apply the tolerance rule; returns the number of points that needed the
+    rounding-error floor and the number that needed exact arbitration."""
     err = np.abs(gpu - ref)
-    lim = rel * np.maximum(np.abs(ref), floor * size)
-    bad = np.nonzero(~(err <= lim))[0]
+    bad = np.nonzero(~(err <= rel * np.abs(ref)))[0]
     if bad.size == 0:
-        return 0
-    assert bad.size <= max(3, len(gpu) // 1000), (
-        f"{label}: {bad.size} of {len(gpu)} points outside tolerance, first {bad[:5]}, "
-        f"err {err[bad[:5]]}, lim {lim[bad[:5]]}")
-    ex = exact_c(k[bad], e[bad])
-    for t, idx in enumerate(bad):
+        return 0, 0
+    ub = error_bound_c(k[bad], e[bad])
+    still = bad[~(err[bad] <= rel * np.abs(ref[bad]) + 2 * ub)]
+    if still.size == 0:
+        return bad.size, 0
+    assert still.size <= max(3, len(gpu) // 1000), (
+        f"{label}: {still.size} of {len(gpu)} points outside tolerance, first {still[:5]}, "
+        f"err {err[still[:5]]}, |ref| {np.abs(ref[still[:5]])}")
+    ex = exact_c(k[still], e[still])
+    for t, idx in enumerate(still):
         e_gpu = abs(gpu[idx] - ex[t])
         e_orc = abs(ref[idx] - ex[t])
         assert e_gpu <= max(rel * abs(ex[t]), 4 * e_orc), (
             f"{label}: point {idx}: gpu {gpu[idx]} oracle {ref[idx]} exact {ex[t]}")
-    return bad.size
+    return bad.size, still.size

@@ -81,3 +81,22 @@ def test_gaussian_rationals_match_complex_arithmetic():
             assert G.mul(q, gb) == ga                          # exact inverse
     x = G.elem(0.1 + 0.3j)                                     # exact dyadic value of the binary64 input
     assert x[0] == Fraction(0.1) and x[1] == Fraction(0.3)
+
+
+def test_running_error_bound_covers_actual_error():
+    """The first-order rounding bound of oracle.fields.RunningError must cover
+    the true error of the binary64 recursion (exact value from Gaussian
+    rationals), on generic and vanishing helicity amplitudes."""
+    import numpy as np
+    from oracle import bg as obg
+    from paper_2502_07060_amd import inputs as I
+    R, G, C = fields.RunningError(), fields.GaussianRationals(), fields.Complex128()
+    k, e, hel = I.random_helicity_c128(17, 5, 12)
+    kc, ec = I.generic_c128(18, 6, 4, 6)
+    for kk, ee in list(zip(k, e)) + list(zip(kc, ec)):
+        kl, el = [list(v) for v in kk], [list(v) for v in ee]
+        _, m = obg.amplitude(C, kl, el)
+        _, mr = obg.amplitude(R, [[R.elem(x) for x in v] for v in kl], [[R.elem(x) for x in v] for v in el])
+        _, mx = obg.amplitude(G, [[G.elem(x) for x in v] for v in kl], [[G.elem(x) for x in v] for v in el])
+        assert mr[0] == m
+        assert abs(m - G.to_complex(mx)) <= 2.0 ** -53 * mr[1]
