@@ -128,6 +128,17 @@ def run_workload(kind: str, steps: int, warmup: int):
     }
 
 
+def calibrate_copy(mib: int):
+    if mib <= 0:
+        return
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +146,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6144)
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6"], default="both",
+                    help="restrict to one workload (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, run one device-to-device copy of MIB MiB: a plain copy "
+                         "kernel of known traffic that scales hardware byte counters")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the recursion shards by point range with no "
@@ -143,8 +159,14 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if a.workload != "both":
+        r = run_workload(a.workload, a.steps, a.warmup)
+        calibrate_copy(a.calibrate_copy)
+        print(json.dumps({"workload": a.workload, **r}), flush=True)
+        return
     main_run = run_workload("c8_d4", a.steps, a.warmup)
     fp_run = run_workload("fp8_d6", a.steps, a.warmup)
+    calibrate_copy(a.calibrate_copy)
     line = {
         "metric": "amplitudes/s at n=8 (C d=4, F_p d=6); served p50/p99 latency vs plain launch",
         "value": main_run["value"],
