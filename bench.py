@@ -32,6 +32,34 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64
 INT_MAD_PEAK_TOPS = 39.3         # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one v_mad_u64_u32 per lane-cycle
 
 
+def kernel_source_digest() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2502_07060_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if "=" in line:
+            k, v = (x.strip() for x in line.split("=", 1))
+            vals[k] = v
+    if vals.get("source_digest") != kernel_source_digest() or kind not in vals:
+        return None
+    return int(vals[kind])
+
+
 def work_per_amplitude(n: int, d: int) -> int:
     R = (n - 1) * (n - 2) // 2 - 1
     return d * (6 * math.comb(n, 3) + 4 * math.comb(n, 4) + 2 * R + 1)
@@ -113,11 +141,11 @@ def run_workload(kind: str, steps: int, warmup: int):
     if w["field"] == "fp":
         achieved = W * npts / (launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": INT_MAD_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / INT_MAD_PEAK_TOPS, "traffic": None}
+                "frac": achieved / INT_MAD_PEAK_TOPS, "traffic": measured_traffic(kind)}
     else:
         achieved = 8 * W * npts / (launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(kind)}
     return {
         "value": npts * steps / (total_ms * 1e-3),
         "ms_per_step": total_ms / steps,
