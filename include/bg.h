@@ -113,6 +113,83 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p,
                      const uint32_t* momenta, const uint32_t* pols,
                      uint32_t* out, uint8_t* status, void* hip_stream);
 
+/*
+ * Batched form: many (field, n, d) groups in one call.  Each group has the
+ * layout and meaning of one bg_amplitudes_* call; every group is validated
+ * before anything is enqueued (the first invalid group's error is returned).
+ * Groups run the kernel variant selected for their (field, n, d), longest
+ * first, spread over internal streams that fork from and join back to
+ * hip_stream: results are valid once hip_stream has been synchronised.
+ * Groups must not overlap in their outputs.
+ */
+typedef struct {
+  int field;            /* BG_FIELD_C128 or BG_FIELD_FP                         */
+  int n, d;
+  uint32_t p;           /* prime, F_p groups only                               */
+  int64_t npts, ld;
+  const void* momenta;  /* complex128 or uint32 [n][d][ld], device            */
+  const void* pols;     /* same layout                                          */
+  void* out;            /* complex128 or uint32 [npts], device                  */
+  uint8_t* status;      /* uint8 [npts] or NULL                                 */
+} bg_group;
+
+int bg_batch_run(const bg_group* groups, int ngroups, void* hip_stream);
+
+/*
+ * A batch plan records the launches of a fixed set of groups (pointers and
+ * sizes fixed, kernel variants as selected at creation) as one hipGraph of
+ * independent kernel nodes; bg_batch_plan_launch replays it on hip_stream with
+ * a single graph launch.  Plans own no device memory.
+ */
+typedef struct bg_batch_plan bg_batch_plan;
+int bg_batch_plan_create(const bg_group* groups, int ngroups, bg_batch_plan** plan);
+int bg_batch_plan_launch(bg_batch_plan* plan, void* hip_stream);
+int bg_batch_plan_destroy(bg_batch_plan* plan);
+
+/*
+ * Kernel variants (tuning interface).  Several kernels may be compiled for one
+ * (field, n, d): lanes per point, components per lane, per-point tables in
+ * registers or LDS, or the runtime-n kernel.  The library picks one by
+ * default; a tuner may measure them and pin one.  Selections are process-wide
+ * and thread safe.
+ */
+typedef struct {
+  int index;            /* pass to bg_select_variant                           */
+  int lanes;            /* lanes cooperating on one point                      */
+  int comps_per_lane;   /* Lorentz components held by each lane (>= d / lanes) */
+  int lds_tables;       /* per-point scalar and momentum tables in LDS          */
+  int generic;          /* runtime-n kernel (tables in LDS, one point per lane) */
+  int selected;         /* 1 if this variant is the one currently in use        */
+} bg_variant_info;
+
+/* Fills up to cap entries for (field, n, d); returns the number available
+ * (possibly > cap) or a negative error code. */
+int bg_variants(int field, int n, int d, bg_variant_info* out, int cap);
+
+/* Pins variant `index` (from bg_variants) for (field, n, d); index -1 restores
+ * the default choice.  BG_EINVAL if the index does not fit (field, n, d). */
+int bg_select_variant(int field, int n, int d, int index);
+
+/*
+ * bg_autotune -- times every variant compiled for (field, n, d) on npts
+ * synthetic points (uniform residues mod p, or complex values with parts in
+ * [-1, 1)), reps launches each after one warm-up, on hip_stream; pins the
+ * fastest and returns its index (>= 0) or a negative error code.  ms_out
+ * (may be NULL) receives the time per launch of each variant in bg_variants
+ * order, up to cap entries.  Allocates and frees its own device buffers; it
+ * synchronises the stream.  p is ignored for the complex field.
+ */
+int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps,
+                double* ms_out, int cap, void* hip_stream);
+
+/* Writes the pinned selections to a text file (one line per (field, n, d),
+ * naming the kernel by lanes, components per lane, LDS tables, generic). */
+int bg_tune_save(const char* path);
+
+/* Applies selections written by bg_tune_save; returns how many matched a
+ * compiled kernel, or a negative error code. */
+int bg_tune_load(const char* path);
+
 /* Human-readable text for a return code (static storage). */
 const char* bg_strerror(int code);
 

@@ -34,6 +34,16 @@ _SIGNATURES = {
     "bg_amplitudes_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "bg_select_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "bg_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_int64,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "bg_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "bg_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "bg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "bg_version": (ctypes.c_int, []),
 }
@@ -72,6 +82,52 @@ def strerror(code: int) -> str:
 
 def bg_version() -> int:
     return lib().bg_version()
+
+
+class bg_variant_info(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_int), ("lanes", ctypes.c_int), ("comps_per_lane", ctypes.c_int),
+                ("lds_tables", ctypes.c_int), ("generic", ctypes.c_int), ("selected", ctypes.c_int)]
+
+
+def bg_variants(field: int, n: int, d: int):
+    """List of dicts describing the kernels compiled for (field, n, d)."""
+    cnt = lib().bg_variants(field, n, d, None, 0)
+    if cnt < 0:
+        raise BGError(cnt, "bg_variants")
+    arr = (bg_variant_info * max(cnt, 1))()
+    lib().bg_variants(field, n, d, ctypes.cast(arr, ctypes.c_void_p), cnt)
+    return [{k: getattr(arr[i], k) for k, _ in bg_variant_info._fields_} for i in range(cnt)]
+
+
+def bg_select_variant(field: int, n: int, d: int, index: int) -> None:
+    rc = lib().bg_select_variant(field, n, d, index)
+    if rc != BG_OK:
+        raise BGError(rc, "bg_select_variant")
+
+
+def bg_autotune(field: int, n: int, d: int, p: int = 0, npts: int = 1 << 18, reps: int = 5, stream=None):
+    """Time every variant for (field, n, d), pin the fastest; returns
+    (chosen index, [(variant dict, ms per launch), ...])."""
+    vs = bg_variants(field, n, d)
+    ms = (ctypes.c_double * max(len(vs), 1))()
+    rc = lib().bg_autotune(field, n, d, ctypes.c_uint32(p), npts, reps, ctypes.cast(ms, ctypes.c_void_p),
+                           len(vs), _stream_ptr(stream))
+    if rc < 0:
+        raise BGError(rc, "bg_autotune")
+    return rc, [(v, ms[i]) for i, v in enumerate(vs)]
+
+
+def bg_tune_save(path: str) -> None:
+    rc = lib().bg_tune_save(path.encode())
+    if rc != BG_OK:
+        raise BGError(rc, "bg_tune_save")
+
+
+def bg_tune_load(path: str) -> int:
+    rc = lib().bg_tune_load(path.encode())
+    if rc < 0:
+        raise BGError(rc, "bg_tune_load")
+    return rc
 
 
 def _stream_ptr(stream):
@@ -146,3 +202,64 @@ def bg_amplitudes_fp(momenta, pols, p, out=None, status=None, npts=None, stream=
     if check and rc != BG_OK:
         raise BGError(rc, "bg_amplitudes_fp")
     return out, status
+
+
+# ----------------------------------------------------------------------------
+# batched form
+# ----------------------------------------------------------------------------
+
+class bg_group(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_int), ("n", ctypes.c_int), ("d", ctypes.c_int), ("p", ctypes.c_uint32),
+                ("npts", ctypes.c_int64), ("ld", ctypes.c_int64), ("momenta", ctypes.c_void_p),
+                ("pols", ctypes.c_void_p), ("out", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+def make_group(momenta, pols, out, status=None, p=0, npts=None):
+    """A bg_group for device tensors laid out as for bg_amplitudes_* (field
+    from the dtype: complex128 -> C, 32-bit integers -> F_p with prime p)."""
+    import torch
+    n, d, ld = momenta.shape
+    field = BG_FIELD_C128 if momenta.dtype == torch.complex128 else BG_FIELD_FP
+    return bg_group(field, n, d, p if field == BG_FIELD_FP else 0, ld if npts is None else int(npts), ld,
+                    momenta.data_ptr(), pols.data_ptr(), out.data_ptr(),
+                    status.data_ptr() if status is not None else None)
+
+
+def _group_array(groups):
+    arr = (bg_group * max(len(groups), 1))(*groups)
+    return arr
+
+
+def bg_batch_run(groups, stream=None) -> None:
+    arr = _group_array(groups)
+    rc = lib().bg_batch_run(ctypes.cast(arr, ctypes.c_void_p), len(groups), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_batch_run")
+
+
+class BatchPlan:
+    """A recorded batch (hipGraph); launch() replays it on a stream."""
+
+    def __init__(self, groups):
+        self._groups = _group_array(groups)   # keep the descriptors alive with the plan
+        self._h = ctypes.c_void_p()
+        rc = lib().bg_batch_plan_create(ctypes.cast(self._groups, ctypes.c_void_p), len(groups),
+                                        ctypes.byref(self._h))
+        if rc != BG_OK:
+            raise BGError(rc, "bg_batch_plan_create")
+
+    def launch(self, stream=None) -> None:
+        rc = lib().bg_batch_plan_launch(self._h, _stream_ptr(stream))
+        if rc != BG_OK:
+            raise BGError(rc, "bg_batch_plan_launch")
+
+    def close(self) -> None:
+        if self._h:
+            lib().bg_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

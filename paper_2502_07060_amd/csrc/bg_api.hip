@@ -11,6 +11,8 @@
 
 namespace bg {
 
+bool is_pinned(int field, int n, int d);
+
 std::vector<Variant>& registry() {
   static std::vector<Variant> r;
   return r;
@@ -64,9 +66,12 @@ FpConst make_fp_const(uint32_t p) {
   uint32_t inv = p;  // Newton iteration for p^-1 mod 2^32 (p odd)
   for (int i = 0; i < 5; ++i) inv *= 2u - p * inv;
   k.pinv = inv;
-  const uint64_t R = (uint64_t(1) << 32) % p;
-  k.c32 = balanced(R, p);
-  k.one = balanced(R, p);
+  k.negp = -(int32_t)p;
+  const uint64_t c32 = (uint64_t(1) << 32) % p;
+  const uint64_t R = (unsigned __int128)c32 * c32 % p;  // 2^64 mod p
+  k.c32 = balanced(c32, p);
+  k.c64 = balanced(R, p);
+  k.one = k.c64;
   k.two = balanced(2 * R, p);
   k.inv2 = balanced((unsigned __int128)R * ((p + 1) / 2) % p, p);
   const uint64_t R2 = (unsigned __int128)R * R % p;
@@ -77,20 +82,61 @@ FpConst make_fp_const(uint32_t p) {
 // ---------------------------------------------------------------------------
 // variant choice
 // ---------------------------------------------------------------------------
+// Default lanes per point, from timings on gfx950 at n = 8 (F_p d = 6: two
+// lanes 0.70 ms vs one lane 0.80 ms per 2^20 points; complex d = 4: two lanes
+// 0.92 ms vs four 1.10 ms); bg_autotune measures the rest.
 static int preferred_lanes(int field, int N, int d) {
-  if (field == FIELD_FP) return 1;
-  // complex: one lane per point only while the current table is small
-  return (N <= 3 && d <= 4) ? 1 : 4;
+  (void)field;
+  (void)N;
+  (void)d;
+  return 2;
 }
 
+static bool fits(const Variant& v, int field, int n, int d) {
+  if (v.field != field) return false;
+  if (v.generic) return v.DL >= d;
+  return v.N == n - 1 && v.DL * v.L >= d;
+}
+
+struct Pin {
+  int field, n, d, index;
+};
+static std::mutex g_pin_mu;
+static std::vector<Pin> g_pins;
+
+static int pinned(int field, int n, int d) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  for (const Pin& p : g_pins)
+    if (p.field == field && p.n == n && p.d == d) return p.index;
+  return -1;
+}
+
+bool is_pinned(int field, int n, int d) { return pinned(field, n, d) >= 0; }
+
+const Variant* default_variant(int field, int n, int d);
+
 const Variant* choose_variant(int field, int n, int d) {
+  const int idx = pinned(field, n, d);
+  if (idx >= 0 && idx < (int)registry().size() && fits(registry()[idx], field, n, d))
+    return &registry()[idx];
+  return default_variant(field, n, d);
+}
+
+const Variant* default_variant(int field, int n, int d) {
   const int N = n - 1;
   const int L = preferred_lanes(field, N, d);
   const int need = (d + L - 1) / L;
   const Variant* best = nullptr;
   for (const Variant& v : registry()) {
     if (v.generic || v.field != field || v.N != N || v.L != L || v.DL < need) continue;
+    if (best && best->DL == v.DL && !v.lds_tables) continue;  // prefer the LDS-table form on ties
     if (!best || v.DL < best->DL) best = &v;
+  }
+  if (best) return best;
+  for (const Variant& v : registry()) {  // any register kernel that fits, fewest padded slots
+    if (v.generic || !fits(v, field, n, d)) continue;
+    if (!best || v.DL * v.L < best->DL * best->L || (v.DL * v.L == best->DL * best->L && v.L < best->L))
+      best = &v;
   }
   if (best) return best;
   for (const Variant& v : registry()) {
@@ -120,11 +166,11 @@ static int max_lds_per_block() {
   return v;
 }
 
-int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
-           void* out, uint8_t* status, const FpConst& fp, hipStream_t stream) {
+int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
+            void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec) {
   const Variant* v = choose_variant(field, n, d);
   if (!v) return BG_ENOTIMPL;
-  LaunchArgs a;
+  LaunchArgs& a = spec.args;
   a.momenta = momenta;
   a.pols = pols;
   a.out = out;
@@ -133,16 +179,19 @@ int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* moment
   a.ld = ld;
   a.d = d;
   a.fp = fp;
+  spec.fn = v->fn;
+  spec.generic = v->generic;
+  spec.N = n - 1;
   if (!v->generic) {
     const int64_t threads = npts * v->L;
     const int64_t blocks = (threads + v->block - 1) / v->block;
     if (blocks > 0x7FFFFFFF) return BG_EINVAL;
-    void* args[] = {&a};
-    hipError_t e = hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(v->block), args, 0, stream);
-    return e == hipSuccess ? BG_OK : BG_EHIP;
+    spec.grid = (unsigned)blocks;
+    spec.block = (unsigned)v->block;
+    spec.shmem = 0;
+    return BG_OK;
   }
-  const int N = n - 1;
-  const size_t per = generic_bytes_per_point(field, N, v->DL);
+  const size_t per = generic_bytes_per_point(field, n - 1, v->DL);
   const int maxlds = max_lds_per_block();
   int P = (int)std::min<size_t>(256, (size_t)maxlds / per);
   if (P >= 64) P = P / 64 * 64;
@@ -155,10 +204,25 @@ int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* moment
   }
   const int64_t blocks = (npts + P - 1) / P;
   if (blocks > 0x7FFFFFFF) return BG_EINVAL;
-  int Narg = N;
-  void* args[] = {&a, &Narg};
-  hipError_t e = hipLaunchKernel(v->fn, dim3((unsigned)blocks), dim3(P), args, shmem, stream);
+  spec.grid = (unsigned)blocks;
+  spec.block = (unsigned)P;
+  spec.shmem = (unsigned)shmem;
+  return BG_OK;
+}
+
+int enqueue(LaunchSpec& spec, hipStream_t stream) {
+  void* args_reg[] = {&spec.args};
+  void* args_gen[] = {&spec.args, &spec.N};
+  hipError_t e = hipLaunchKernel(spec.fn, dim3(spec.grid), dim3(spec.block),
+                                 spec.generic ? args_gen : args_reg, spec.shmem, stream);
   return e == hipSuccess ? BG_OK : BG_EHIP;
+}
+
+int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
+           void* out, uint8_t* status, const FpConst& fp, hipStream_t stream) {
+  LaunchSpec spec;
+  const int rc = prepare(field, n, d, npts, ld, momenta, pols, out, status, fp, spec);
+  return rc == BG_OK ? enqueue(spec, stream) : rc;
 }
 
 static int check_common(int n, int d, int64_t npts, int64_t ld) {
@@ -201,6 +265,43 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const u
   const bg::FpConst k = bg::make_fp_const(p);
   return bg::launch(bg::FIELD_FP, n, d, npts, ld, momenta, pols, out, status, k,
                     static_cast<hipStream_t>(hip_stream));
+}
+
+int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {
+  if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
+  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
+  const bg::Variant* cur = bg::choose_variant(field, n, d);
+  int count = 0;
+  const auto& reg = bg::registry();
+  for (int i = 0; i < (int)reg.size(); ++i) {
+    if (!bg::fits(reg[i], field, n, d)) continue;
+    if (out && count < cap) {
+      bg_variant_info& o = out[count];
+      o.index = i;
+      o.lanes = reg[i].L;
+      o.comps_per_lane = reg[i].DL;
+      o.lds_tables = reg[i].lds_tables ? 1 : 0;
+      o.generic = reg[i].generic ? 1 : 0;
+      o.selected = (&reg[i] == cur) ? 1 : 0;
+    }
+    ++count;
+  }
+  return count;
+}
+
+int bg_select_variant(int field, int n, int d, int index) {
+  if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
+  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
+  if (index >= 0 && (index >= (int)bg::registry().size() || !bg::fits(bg::registry()[index], field, n, d)))
+    return BG_EINVAL;
+  std::lock_guard<std::mutex> lk(bg::g_pin_mu);
+  for (auto it = bg::g_pins.begin(); it != bg::g_pins.end(); ++it)
+    if (it->field == field && it->n == n && it->d == d) {
+      bg::g_pins.erase(it);
+      break;
+    }
+  if (index >= 0) bg::g_pins.push_back({field, n, d, index});
+  return BG_OK;
 }
 
 const char* bg_strerror(int code) {

@@ -51,7 +51,7 @@ struct FpField {
                        [](auto ctrl, A v) { return (A)dpp_u64<decltype(ctrl)::value>((uint64_t)v); });
       t = fp_fold(t, k);
     }
-    return fp_redc(t, k);
+    return fp_redc2(t, k);
   }
 
   // -(x.y) for primed x (x' slots already carry the time sign)
@@ -76,7 +76,8 @@ struct FpField {
     return finish_dot(t, DL > 7 ? 5 + (DL - 7) : DL);
   }
 
-  // -(x.y) - z  (z a balanced Montgomery value, added in the R^2 domain)
+  // -(x.y) - z  (z a balanced Montgomery value, lifted into the product
+  // accumulator by the factor R mod p)
   __device__ __forceinline__ S ndot_sub(const E* xp, const E* y, S z) const {
     A t = 0;
 #pragma unroll
@@ -85,11 +86,11 @@ struct FpField {
       if (c == 5) t = fp_fold(t, k);
     }
     if constexpr (L == 1) {
-      t = mad64(-z, k.c32, t);
-      return fp_redc(fp_fold(t, k), k);
+      t = mad64(-z, k.c64, t);
+      return fp_redc2(fp_fold(t, k), k);
     } else {
       // the scalar is added once per group, on group lane 0
-      t = mad64(time_lane ? -z : 0, k.c32, t);
+      t = mad64(time_lane ? -z : 0, k.c64, t);
       return finish_dot(t, DL + 1 > 7 ? 8 : DL + 1);
     }
   }
@@ -102,7 +103,7 @@ struct FpField {
 #pragma unroll
     for (int i = 0; i < DL; ++i) K[i] = fp_fold(K[i], k);
   }
-  __device__ __forceinline__ E finish(A K) const { return fp_redc(fp_fold(K, k), k); }
+  __device__ __forceinline__ E finish(A K) const { return fp_redc2(fp_fold(K, k), k); }
   __device__ __forceinline__ E mul(E x, S c) const { return fp_mul(x, c, k); }
   __device__ __forceinline__ S smul(S a, S b) const { return fp_mul(a, b, k); }
 };

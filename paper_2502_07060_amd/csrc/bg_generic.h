@@ -297,6 +297,7 @@ __global__ __launch_bounds__(256) void bg_generic_kernel(LaunchArgs a, int N) {
   if constexpr (Fld::exact) {
     Fld F(a.fp, 0);
     G.run(F, a, q, bad, singular, res);
+    bad = bad >= (uint32_t)a.fp.p ? 1u : 0u;
     if (valid) {
       uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
       uint32_t outv = 0xFFFFFFFFu;

@@ -34,6 +34,10 @@
 #include "bg_common.h"
 #include "bg_fields.h"
 
+#ifndef BG_SPLIT_BARRIER
+#define BG_SPLIT_BARRIER 1
+#endif
+
 namespace bg {
 
 enum { PT_OK = 0, PT_SINGULAR = 1, PT_BADRESIDUE = 2 };
@@ -52,17 +56,24 @@ struct LaunchArgs {
 // ---------------------------------------------------------------------------
 // loads
 // ---------------------------------------------------------------------------
+// Every load is unconditional (a padded component reads row 0 and is zeroed
+// afterwards), so the compiler can issue all of a point's loads back to back
+// and wait once.  On F_p the largest raw residue seen is kept in `maxraw`;
+// the point has a bad residue iff it ends up >= p.
 template <class Fld>
 struct Loader;
 
 template <int DL, int L>
 struct Loader<FpField<DL, L>> {
   __device__ static int32_t get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
-                                uint32_t& bad) {
-    if (mu >= a.d) return 0;
-    uint32_t x = static_cast<const uint32_t*>(base)[((int64_t)l * a.d + mu) * a.ld + q];
-    bad |= (x >= (uint32_t)a.fp.p) ? 1u : 0u;
-    return fp_from_canonical(x < (uint32_t)a.fp.p ? x : 0u, a.fp);
+                                uint32_t& maxraw) {
+    const bool in = mu < a.d;
+    const uint32_t x =
+        static_cast<const uint32_t*>(base)[((int64_t)l * a.d + (in ? mu : 0)) * a.ld + q];
+    const uint32_t xi = in ? x : 0u;
+    maxraw = maxraw > xi ? maxraw : xi;
+    const uint32_t xc = xi < (uint32_t)a.fp.p ? xi : 0u;
+    return fp_from_canonical(xc, a.fp);
   }
 };
 
@@ -70,9 +81,10 @@ template <int DL, int L>
 struct Loader<C128Field<DL, L>> {
   __device__ static cplx get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                              uint32_t&) {
-    if (mu >= a.d) return {0.0, 0.0};
-    const double2 v = static_cast<const double2*>(base)[((int64_t)l * a.d + mu) * a.ld + q];
-    return {v.x, v.y};
+    const bool in = mu < a.d;
+    const double2 v =
+        static_cast<const double2*>(base)[((int64_t)l * a.d + (in ? mu : 0)) * a.ld + q];
+    return in ? cplx{v.x, v.y} : cplx{0.0, 0.0};
   }
 };
 
@@ -84,10 +96,11 @@ struct Inverses {};
 
 template <int DL, int L, int NP>
 struct Inverses<FpField<DL, L>, NP> {
-  int32_t inv[NP > 0 ? NP : 1];
   // Montgomery batch inversion (Montgomery 1987): one Fermat power for all NP
-  // values; a zero anywhere makes the point singular.
-  __device__ bool compute(const FpField<DL, L>& F, int32_t (&y)[NP > 0 ? NP : 1]) {
+  // values; a zero anywhere makes the point singular.  inv(s) receives
+  // 2/P_S^2 for y(s) = -P_S^2.
+  template <class Tab>
+  __device__ static bool compute(const FpField<DL, L>& F, int32_t (&y)[NP > 0 ? NP : 1], Tab& inv) {
     if constexpr (NP == 0) {
       return false;
     } else {
@@ -103,19 +116,42 @@ struct Inverses<FpField<DL, L>, NP> {
       t = fp_mul(t, -F.k.two, F.k);
 #pragma unroll
       for (int s = NP - 1; s >= 0; --s) {
-        inv[s] = s == 0 ? t : fp_mul(t, pre[s - 1], F.k);
+        inv.set(s, s == 0 ? t : fp_mul(t, pre[s - 1], F.k));
         if (s > 0) t = fp_mul(t, y[s], F.k);
       }
       return zero;
     }
   }
-  __device__ __forceinline__ int32_t get(int s) const { return inv[s]; }
+};
+
+// ---------------------------------------------------------------------------
+// per-point tables that may live in registers or in LDS
+// ---------------------------------------------------------------------------
+// Store<T, SLOTS, LDS>: SLOTS values of T for this lane (or this point).  In
+// register mode a plain array (indexed with compile-time slots after
+// unrolling); in LDS mode a [slot][column] array in shared memory, with one
+// column per lane (vectors) or per point (scalars shared by the L lanes of a
+// point: every lane of the group writes the same value, and the group lies in
+// one wavefront, so no barrier is needed).
+template <class T, int SLOTS, bool LDS>
+struct Store {
+  T r[SLOTS > 0 ? SLOTS : 1];
+  __device__ __forceinline__ T get(int s) const { return r[s]; }
+  __device__ __forceinline__ void set(int s, T v) { r[s] = v; }
+};
+
+template <class T, int SLOTS>
+struct Store<T, SLOTS, true> {
+  T* base;
+  int stride;
+  __device__ __forceinline__ T get(int s) const { return base[s * stride]; }
+  __device__ __forceinline__ void set(int s, T v) { base[s * stride] = v; }
 };
 
 // ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
-template <class Fld, int N, int DL, int L>
+template <class Fld, int N, int DL, int L, bool LT = false>
 struct Recursion {
   using E = typename Fld::E;
   using S = typename Fld::S;
@@ -124,26 +160,56 @@ struct Recursion {
   static constexpr int NCUR = R::ncur;   // non-root currents
   static constexpr int NP = R::nprop;    // propagators
 
+  // LDS footprint of the tables when LT: scalars per point, vector slots per lane
+  static constexpr int kScalars = Fld::exact ? 2 * NP + NCUR : NP;
+  static constexpr int kVecSlots = (Fld::exact ? N + 1 : N) * DL;
+
+  template <int BLOCK>
+  struct Lds {
+    S scal[LT ? kScalars : 1][BLOCK / L];
+    E vec[LT ? kVecSlots : 1][BLOCK];
+  };
+
+  template <class Tab>
+  __device__ static void bind(Tab& t, void* base, int stride) {
+    if constexpr (LT) {
+      t.base = static_cast<decltype(t.base)>(base);
+      t.stride = stride;
+    }
+  }
+
+  template <int BLOCK>
   __device__ static void run(const Fld& F, const LaunchArgs& a, int64_t q, int s, uint32_t& bad,
-                             bool& singular, S& result) {
+                             bool& singular, S& result, Lds<BLOCK>* lds) {
     constexpr bool kFp = Fld::exact;
     E J[NCUR][DL];
-    S nDh[NCUR];                 // -Dh(X) for |X| >= 2 (indexed by range index)
     E epsn[DL];
-    // F_p: prefix sums Q_l and nc(X) = -(P_X . J_X); exact, so P_S = Q_{j+1} - Q_i.
-    E Q[kFp ? N + 1 : 1][DL];
-    S nc[kFp ? NCUR : 1];
-    // complex: primed momenta k'_l and the primed column P'_{i..j} for the
-    // current right end j, both built by left-to-right sums exactly as the
-    // definition of P_{i,j} reads (no differences of large partial sums).
-    E kp[kFp ? 1 : N][DL];
+    // per-point scalars: -Dh(X) for |X| >= 2 (by propagator index), and on F_p
+    // nc(X) = -(P_X . J_X) (by range index) and the propagator inverses
+    Store<S, NP, LT> nDh;
+    Store<S, kFp ? NCUR : 0, LT> nc;
+    Store<S, kFp ? NP : 0, LT> inv;
+    // F_p: prefix sums Q_l (exact, so P_S = Q_{j+1} - Q_i); complex: primed
+    // momenta k'_l.  Slot l * DL + c.
+    Store<E, kVecSlots, LT> mom;
+    // complex: primed column P'_{i..j} for the current right end j, built by
+    // left-to-right sums exactly as the definition of P_{i,j} reads (no
+    // differences of large partial sums)
     E col[kFp ? 1 : N][DL];
     const int mu0 = s * DL;
+    if constexpr (LT) {
+      const int pcol = (int)(threadIdx.x / L), lcol = (int)threadIdx.x;
+      bind(nDh, &lds->scal[0][pcol], BLOCK / L);
+      bind(nc, &lds->scal[NP][pcol], BLOCK / L);
+      bind(inv, &lds->scal[NP + (kFp ? NCUR : 0)][pcol], BLOCK / L);
+      bind(mom, &lds->vec[0][lcol], BLOCK);
+    }
+    auto Qg = [&](int l, int c) { return mom.get(l * DL + c); };
 
     // ---- a1: loads; a2: sub-range momenta ----------------------------------
     if constexpr (kFp) {
 #pragma unroll
-      for (int c = 0; c < DL; ++c) Q[0][c] = E{};
+      for (int c = 0; c < DL; ++c) mom.set(c, E{});
     }
     static_for<0, N>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
@@ -155,20 +221,19 @@ struct Recursion {
       }
       k[0] = F.prime0(k[0]);
       if constexpr (kFp) {
-        nc[R::idx(l, l)] = F.ndot(k, J[R::idx(l, l)]);
+        nc.set(R::idx(l, l), F.ndot(k, J[R::idx(l, l)]));
         k[0] = F.prime0(k[0]);
 #pragma unroll
-        for (int c = 0; c < DL; ++c) Q[l + 1][c] = F.eadd(Q[l][c], k[c]);
+        for (int c = 0; c < DL; ++c) mom.set((l + 1) * DL + c, F.eadd(Qg(l, c), k[c]));
       } else {
 #pragma unroll
-        for (int c = 0; c < DL; ++c) kp[l][c] = k[c];
+        for (int c = 0; c < DL; ++c) mom.set(l * DL + c, k[c]);
       }
     });
 #pragma unroll
     for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::get(a, a.pols, N, mu0 + c, q, bad);
 
     // ---- a3/a4 (F_p): all propagator denominators, one batched inversion -----
-    [[maybe_unused]] Inverses<Fld, NP> invs;
     if constexpr (kFp) {
       int32_t y[NP > 0 ? NP : 1];  // y(S) = -P_S^2
       static_for<2, N>([&](auto mc) {
@@ -177,15 +242,15 @@ struct Recursion {
           constexpr int i = decltype(ic)::value;
           constexpr int j = i + m - 1;
           E Pp[DL], P[DL];
-          primedP<i, j>(F, Q, Pp);
+          primedP<i, j>(F, mom, Pp);
           unprime(F, Pp, P);
           y[R::pidx(i, j)] = F.ndot(Pp, P);
         });
       });
-      singular = invs.compute(F, y);
+      singular = Inverses<Fld, NP>::compute(F, y, inv);
     } else {
 #pragma unroll
-      for (int c = 0; c < DL; ++c) col[0][c] = kp[0][c];
+      for (int c = 0; c < DL; ++c) col[0][c] = Qg(0, c);
     }
 
     // ---- a5: the recursion, column by column (right end j), each column from
@@ -196,18 +261,21 @@ struct Recursion {
         // column j: P'_{i..j} = P'_{i..j-1} + k'_j
         static_for<0, j>([&](auto ic) {
           constexpr int i = decltype(ic)::value;
+          E kj[DL];
 #pragma unroll
-          for (int c = 0; c < DL; ++c) col[i][c] = F.eadd(col[i][c], kp[j][c]);
+          for (int c = 0; c < DL; ++c) kj[c] = Qg(j, c);
+#pragma unroll
+          for (int c = 0; c < DL; ++c) col[i][c] = F.eadd(col[i][c], kj[c]);
         });
 #pragma unroll
-        for (int c = 0; c < DL; ++c) col[j][c] = kp[j][c];
+        for (int c = 0; c < DL; ++c) col[j][c] = Qg(j, c);
       }
       static_for<0, j>([&](auto ic) {
         constexpr int i = j - 1 - decltype(ic)::value;
         constexpr bool root = (i == 0 && j == N - 1);
         E Pp[DL];
         if constexpr (kFp) {
-          primedP<i, j>(F, Q, Pp);
+          primedP<i, j>(F, mom, Pp);
         } else {
 #pragma unroll
           for (int c = 0; c < DL; ++c) Pp[c] = col[i][c];
@@ -226,15 +294,18 @@ struct Recursion {
           if constexpr (kFp) {
             // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
             // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
-            const S nc2 = F.ndot_sub(Pp, J[ia], nc[ia]);   // -(P_B.J_A)
-            const S nc3 = F.ndot_sub(Pp, J[ib], nc[ib]);   // -(P_A.J_B)
-            F.axpy(K, F.sneg(nDm), Q[t + 1]);
+            const S nc2 = F.ndot_sub(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
+            const S nc3 = F.ndot_sub(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
+            E Qt[DL];
+#pragma unroll
+            for (int c = 0; c < DL; ++c) Qt[c] = Qg(t + 1, c);
+            F.axpy(K, F.sneg(nDm), Qt);
             F.axpy(K, F.sneg(nc2), J[ib]);
             F.axpy(K, nc3, J[ia]);
             F.fold(K);
           } else {
 #pragma unroll
-            for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? kp[i][c] : F.eadd(PA[c], kp[t][c]);
+            for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? Qg(i, c) : F.eadd(PA[c], Qg(t, c));
             const S n2 = F.ndot(col[t + 1], J[ia]);        // -(P_B.J_A)
             const S n3 = F.ndot(PA, J[ib]);                // -(P_A.J_B)
             E v[DL];
@@ -246,15 +317,22 @@ struct Recursion {
             F.axpy(K, n3, J[ia]);
           }
           nDsum = accumulate_scalar(F, nDsum, nDm);
+          split_barrier();
         });
         const S nDhS = half_scalar(F, nDsum);
         if constexpr (kFp) {
           // -Dh(S) (Q_i + Q_{j+1})
-          F.axpy(K, nDhS, Q[i]);
-          F.axpy(K, nDhS, Q[j + 1]);
+          E Qi[DL], Qj[DL];
+#pragma unroll
+          for (int c = 0; c < DL; ++c) {
+            Qi[c] = Qg(i, c);
+            Qj[c] = Qg(j + 1, c);
+          }
+          F.axpy(K, nDhS, Qi);
+          F.axpy(K, nDhS, Qj);
           F.fold(K);
         }
-        if constexpr (!root) nDh[R::idx(i, j)] = nDhS;
+        if constexpr (!root) nDh.set(R::pidx(i, j), nDhS);
 
         // four-gluon vertex: sum (J_A.J_C) J_B, then the Dh terms
         static_for<i, j - 1>([&](auto sc) {
@@ -265,18 +343,19 @@ struct Recursion {
             F.axpy(K, F.sneg(ne), J[R::idx(s1 + 1, t)]);
             constexpr int qn = v4_index<i, j>(s1, t);
             if constexpr (qn % 5 == 4) F.fold(K);
+            split_barrier();
           });
         });
         F.fold(K);
         static_for<i + 1, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
-          F.axpy(K, nDh[R::idx(i, t)], J[R::idx(t + 1, j)]);
+          F.axpy(K, nDh.get(R::pidx(i, t)), J[R::idx(t + 1, j)]);
           if constexpr ((t - i) % 5 == 4) F.fold(K);
         });
         F.fold(K);
         static_for<i, j - 1>([&](auto sc) {
           constexpr int s1 = decltype(sc)::value;
-          F.axpy(K, nDh[R::idx(s1 + 1, j)], J[R::idx(i, s1)]);
+          F.axpy(K, nDh.get(R::pidx(s1 + 1, j)), J[R::idx(i, s1)]);
           if constexpr ((s1 - i) % 5 == 4) F.fold(K);
         });
 
@@ -284,7 +363,7 @@ struct Recursion {
           // J(S) = K' * 2/P_S^2
           S inv2;
           if constexpr (kFp) {
-            inv2 = invs.get(R::pidx(i, j));
+            inv2 = inv.get(R::pidx(i, j));
           } else {
             E P[DL];
             unprime(F, Pp, P);
@@ -294,7 +373,7 @@ struct Recursion {
           constexpr int id = R::idx(i, j);
 #pragma unroll
           for (int c = 0; c < DL; ++c) J[id][c] = F.mul(F.finish(K[c]), inv2);
-          if constexpr (kFp) nc[id] = F.ndot(Pp, J[id]);
+          if constexpr (kFp) nc.set(id, F.ndot(Pp, J[id]));
         } else {
           // a6: returns -(eps_n . K'); the amplitude is M = 2 eps_n . K'
           E Kf[DL];
@@ -312,11 +391,20 @@ struct Recursion {
     P[0] = F.prime0(Pp[0]);
   }
 
+  // Keeps the scheduler from interleaving many splits at once: the current
+  // table is already most of the register file, so unbounded interleaving
+  // turns into spills.
+  __device__ static __forceinline__ void split_barrier() {
+#if BG_SPLIT_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+  }
+
   // primed P_S = Q_{j+1} - Q_i with the time slot negated (F_p)
-  template <int i, int j>
-  __device__ static __forceinline__ void primedP(const Fld& F, const E (&Q)[N + 1][DL], E (&P)[DL]) {
+  template <int i, int j, class Tab>
+  __device__ static __forceinline__ void primedP(const Fld& F, const Tab& Q, E (&P)[DL]) {
 #pragma unroll
-    for (int c = 0; c < DL; ++c) P[c] = F.esub(Q[j + 1][c], Q[i][c]);
+    for (int c = 0; c < DL; ++c) P[c] = F.esub(Q.get((j + 1) * DL + c), Q.get(i * DL + c));
     P[0] = F.prime0(P[0]);
   }
 
@@ -349,8 +437,13 @@ struct Recursion {
   }
 };
 
-template <class Fld, int N, int DL, int L, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void bg_recursion_kernel(LaunchArgs a) {
+// W = minimum waves per SIMD the register allocation must allow (1: the whole
+// register file for one wave; 2: at most 256 registers per lane).
+template <class Fld, int N, int DL, int L, int BLOCK, bool LT, int W>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W)))
+void bg_recursion_kernel(LaunchArgs a) {
+  using Rec = Recursion<Fld, N, DL, L, LT>;
+  __shared__ typename Rec::template Lds<BLOCK> lds;
   const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int s = (int)(g % L);
   const int64_t q0 = g / L;
@@ -361,10 +454,11 @@ __global__ __launch_bounds__(BLOCK) void bg_recursion_kernel(LaunchArgs a) {
   typename Fld::S res;
   if constexpr (Fld::exact) {
     Fld F(a.fp, s);
-    Recursion<Fld, N, DL, L>::run(F, a, q, s, bad, singular, res);
+    Rec::run(F, a, q, s, bad, singular, res, &lds);
     if constexpr (L > 1)
-      bad = group_sum<L>(bad, [](uint32_t x, uint32_t y) { return x | y; },
+      bad = group_sum<L>(bad, [](uint32_t x, uint32_t y) { return x > y ? x : y; },
                          [](auto ctrl, uint32_t v) { return dpp_u32<decltype(ctrl)::value>(v); });
+    bad = bad >= (uint32_t)a.fp.p ? 1u : 0u;
     if (valid && s == 0) {
       uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
       uint32_t outv = 0xFFFFFFFFu;
@@ -380,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void bg_recursion_kernel(LaunchArgs a) {
     }
   } else {
     Fld F(s);
-    Recursion<Fld, N, DL, L>::run(F, a, q, s, bad, singular, res);
+    Rec::run(F, a, q, s, bad, singular, res, &lds);
     if (valid && s == 0) {
       double2 o;
       if (singular) {

@@ -8,6 +8,8 @@
 
 #include <vector>
 
+#include "bg_kernel.h"
+
 namespace bg {
 
 enum : int { FIELD_C128 = 0, FIELD_FP = 1 };
@@ -19,10 +21,29 @@ struct Variant {
   int L;          // lanes per point
   int block;      // threads per block
   bool generic;   // runtime-n kernel with LDS tables
+  bool lds_tables;  // register kernel with per-point tables in LDS
+  int waves;        // minimum waves per SIMD the register allocation allows
   const void* fn;
 };
 
 std::vector<Variant>& registry();
+bool is_pinned(int field, int n, int d);
+
+// A fully prepared launch of one (field, n, d) batch: kernel, grid and the
+// argument block (kept alive by the owner, e.g. a graph plan).
+struct LaunchSpec {
+  const void* fn = nullptr;
+  unsigned grid = 0, block = 0, shmem = 0;
+  bool generic = false;
+  int N = 0;
+  LaunchArgs args;
+};
+
+FpConst make_fp_const(uint32_t p);
+bool is_prime_u32(uint32_t n);
+int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
+            void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec);
+int enqueue(LaunchSpec& spec, hipStream_t stream);
 
 struct Registrar {
   explicit Registrar(const Variant& v) { registry().push_back(v); }
@@ -33,19 +54,20 @@ struct Registrar {
 #define BG_CAT2(a, b) a##b
 #define BG_CAT(a, b) BG_CAT2(a, b)
 
-// register-resident kernel for field FLD (FpField / C128Field), N, DL, L
-#define BG_REGISTER_RECURSION(FIELDTAG, FLD, N_, DL_, L_)                                       \
-  namespace bg {                                                                                \
-  template __global__ void bg_recursion_kernel<FLD<DL_, L_>, N_, DL_, L_, 256>(LaunchArgs);    \
-  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
-      FIELDTAG, N_, DL_, L_, 256, false,                                                        \
-      reinterpret_cast<const void*>(&bg_recursion_kernel<FLD<DL_, L_>, N_, DL_, L_, 256>)});    \
+// register-resident kernel for field FLD (FpField / C128Field), N, DL, L,
+// with the per-point tables in LDS when LT is true, W waves per SIMD
+#define BG_REGISTER_RECURSION(FIELDTAG, FLD, N_, DL_, L_, LT_, W_)                                      \
+  namespace bg {                                                                                        \
+  template __global__ void bg_recursion_kernel<FLD<DL_, L_>, N_, DL_, L_, 256, LT_, W_>(LaunchArgs);   \
+  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                                   \
+      FIELDTAG, N_, DL_, L_, 256, false, LT_, W_,                                                       \
+      reinterpret_cast<const void*>(&bg_recursion_kernel<FLD<DL_, L_>, N_, DL_, L_, 256, LT_, W_>)});   \
   }
 
 #define BG_REGISTER_GENERIC(FIELDTAG, FLD, DMAX_)                                               \
   namespace bg {                                                                                \
   template __global__ void bg_generic_kernel<FLD<DMAX_, 1>, DMAX_>(LaunchArgs, int);            \
   static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
-      FIELDTAG, 0, DMAX_, 1, 0, true,                                                           \
+      FIELDTAG, 0, DMAX_, 1, 0, true, true, 1,                                                  \
       reinterpret_cast<const void*>(&bg_generic_kernel<FLD<DMAX_, 1>, DMAX_>)});                \
   }

@@ -1,0 +1,164 @@
+// Autotuner: times every compiled kernel variant for a (field, n, d) on
+// synthetic device inputs and pins the fastest (see bg_autotune in bg.h).
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "bg.h"
+#include "bg_registry.h"
+
+namespace bg {
+bool is_prime_u32(uint32_t n);
+}
+
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  // splitmix64 finaliser (Steele, Lea, Flood 2014)
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// uniform residues in [0, p) (p > 0) or, for p == 0, complex values with
+// parts in [-1, 1); count = number of 32-bit (F_p) or complex (C) elements
+__global__ void fill_kernel(void* dst, int64_t count, uint32_t p, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t r = mix64(seed ^ (uint64_t)i);
+  if (p) {
+    static_cast<uint32_t*>(dst)[i] = (uint32_t)((r >> 32) % p);
+  } else {
+    const double a = (double)(r >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    const double b = (double)(mix64(r) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    static_cast<double2*>(dst)[i] = make_double2(a, b);
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps, double* ms_out,
+                           int cap, void* hip_stream) {
+  if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
+  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
+  if (npts <= 0 || reps <= 0) return BG_EINVAL;
+  if (field == BG_FIELD_FP && (p < 3 || p >= 0x80000000u || !bg::is_prime_u32(p))) return BG_ENOTPRIME;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int count = bg_variants(field, n, d, nullptr, 0);
+  if (count <= 0) return count < 0 ? count : BG_ENOTIMPL;
+  std::vector<bg_variant_info> vs(count);
+  bg_variants(field, n, d, vs.data(), count);
+  // the current selection, restored if anything fails
+  int prev = -1;
+  for (const auto& v : vs)
+    if (v.selected) prev = v.index;
+
+  const size_t elem = field == BG_FIELD_FP ? 4 : 16;
+  const int64_t nelem = (int64_t)n * d * npts;
+  DevBuf mom, pol, out, sta;
+  if (hipMalloc(&mom.p, nelem * elem) != hipSuccess || hipMalloc(&pol.p, nelem * elem) != hipSuccess ||
+      hipMalloc(&out.p, npts * elem) != hipSuccess || hipMalloc(&sta.p, npts) != hipSuccess)
+    return BG_ENOMEM;
+  const uint32_t fp = field == BG_FIELD_FP ? p : 0;
+  const int64_t blocks = (nelem + 255) / 256;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, mom.p, nelem, fp, 0x1234ull);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pol.p, nelem, fp, 0x5678ull);
+  if (hipGetLastError() != hipSuccess) return BG_EHIP;
+
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return BG_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return BG_EHIP;
+  }
+  auto run = [&]() {
+    if (field == BG_FIELD_FP)
+      return bg_amplitudes_fp(n, d, npts, npts, p, (const uint32_t*)mom.p, (const uint32_t*)pol.p,
+                              (uint32_t*)out.p, (uint8_t*)sta.p, st);
+    return bg_amplitudes_c128(n, d, npts, npts, (const double*)mom.p, (const double*)pol.p, (double*)out.p,
+                              (uint8_t*)sta.p, st);
+  };
+  int rc = BG_OK, best = -1;
+  double best_ms = 1e300;
+  for (int k = 0; k < count && rc == BG_OK; ++k) {
+    bg_select_variant(field, n, d, vs[k].index);
+    rc = run();  // warm-up
+    float ms = 0.f;
+    if (rc == BG_OK && hipEventRecord(e0, st) != hipSuccess) rc = BG_EHIP;
+    for (int r = 0; r < reps && rc == BG_OK; ++r) rc = run();
+    if (rc == BG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = BG_EHIP;
+    const double per = rc == BG_OK ? (double)ms / reps : -1.0;
+    if (ms_out && k < cap) ms_out[k] = per;
+    if (rc == BG_OK && per < best_ms) {
+      best_ms = per;
+      best = vs[k].index;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BG_OK || best < 0) {
+    bg_select_variant(field, n, d, -1);
+    return rc != BG_OK ? rc : BG_EHIP;
+  }
+  bg_select_variant(field, n, d, best);
+  (void)prev;
+  return best;
+}
+
+// Selections as text, one line per pinned (field, n, d):
+//   field n d lanes comps_per_lane lds_tables generic
+// Lines name kernels by their shape, so a file stays valid across builds that
+// register kernels in another order; lines with no matching kernel are skipped.
+extern "C" int bg_tune_save(const char* path) {
+  if (!path) return BG_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return BG_EINVAL;
+  fprintf(f, "# field n d lanes comps_per_lane lds_tables generic\n");
+  bg_variant_info vs[64];
+  for (int field = 0; field <= 1; ++field)
+    for (int n = 3; n <= BG_MAX_N; ++n)
+      for (int d = 1; d <= BG_MAX_D; ++d) {
+        const int c = std::min(64, bg_variants(field, n, d, vs, 64));
+        for (int k = 0; k < c; ++k)
+          if (vs[k].selected && bg::is_pinned(field, n, d))
+            fprintf(f, "%d %d %d %d %d %d %d\n", field, n, d, vs[k].lanes, vs[k].comps_per_lane,
+                    vs[k].lds_tables, vs[k].generic);
+      }
+  fclose(f);
+  return BG_OK;
+}
+
+extern "C" int bg_tune_load(const char* path) {
+  if (!path) return BG_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return BG_EINVAL;
+  char line[256];
+  int applied = 0;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int field, n, d, lanes, dl, lt, gen;
+    if (sscanf(line, "%d %d %d %d %d %d %d", &field, &n, &d, &lanes, &dl, &lt, &gen) != 7) continue;
+    bg_variant_info vs[64];
+    const int c = bg_variants(field, n, d, vs, 64);
+    for (int k = 0; k < std::min(c, 64); ++k)
+      if (vs[k].lanes == lanes && vs[k].comps_per_lane == dl && vs[k].lds_tables == lt && vs[k].generic == gen) {
+        if (bg_select_variant(field, n, d, vs[k].index) == BG_OK) ++applied;
+        break;
+      }
+  }
+  fclose(f);
+  return applied;
+}

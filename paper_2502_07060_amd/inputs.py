@@ -426,6 +426,43 @@ def config_workload(name: str, npts: int | None = None):
     raise KeyError(name)
 
 
+def batched_groups(total: int = 4_000_000, seed: int = 4, ns=range(4, 15), ds=(4, 6, 8, 10),
+                   fields=("c128", "fp"), zipf_s: float = 1.2):
+    """Group shapes and sizes of the mixed batched workload.
+
+    Groups are (field, n, d) over the given ranges; their sizes are a
+    multinomial draw of `total` points with weights proportional to
+    r^-zipf_s over the ranks r = 1..G, ranks assigned to groups by a seeded
+    permutation.  Returns a list of dicts (field, n, d, npts, seed).
+    """
+    rng = np.random.default_rng(seed)
+    shapes = [(f, n, d) for f in fields for n in ns for d in ds]
+    w = np.arange(1, len(shapes) + 1, dtype=float) ** (-zipf_s)
+    w /= w.sum()
+    sizes = rng.multinomial(total, w)
+    order = rng.permutation(len(shapes))
+    out = []
+    for rank, g in enumerate(order):
+        f, n, d = shapes[g]
+        out.append(dict(field=f, n=n, d=d, npts=int(sizes[rank]), seed=int(seed * 1000 + g)))
+    return out
+
+
+def group_inputs(g, p: int = DEFAULT_PRIME):
+    """Inputs for one group of ``batched_groups``: F_p groups use the F_p
+    light-cone generator, complex d = 4 groups spinor-helicity points with
+    random helicities, complex d > 4 groups RAMBO momenta in d dimensions with
+    transverse random polarisations."""
+    m = max(g["npts"], 1)
+    if g["field"] == "fp":
+        k, e = generic_fp(g["seed"], g["n"], g["d"], m, p)
+    elif g["d"] == 4:
+        k, e, _ = random_helicity_c128(g["seed"], g["n"], m)
+    else:
+        k, e = generic_c128(g["seed"], g["n"], g["d"], m)
+    return k[:g["npts"]], e[:g["npts"]]
+
+
 # ----------------------------------------------------------------------------
 # layout
 # ----------------------------------------------------------------------------

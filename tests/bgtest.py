@@ -16,6 +16,7 @@ max(1e-11 |exact|, 4 x the oracle's own error).
 """
 from __future__ import annotations
 
+import atexit
 import multiprocessing as mp
 import os
 
@@ -35,7 +36,16 @@ def pool():
     global _POOL
     if _POOL is None:
         _POOL = mp.get_context("fork").Pool(_workers())
+        atexit.register(_close_pool)
     return _POOL
+
+
+def _close_pool():
+    global _POOL
+    if _POOL is not None:
+        _POOL.terminate()
+        _POOL.join()
+        _POOL = None
 
 
 def _fp_one(args):

@@ -90,3 +90,25 @@ def test_primality_matches_oracle():
     for p in cands:
         rc = call_fp(p=p, npts=0, ld=0)
         assert (rc == bg.BG_OK) == is_prime(p), p
+
+
+def test_variant_listing_and_selection():
+    """Host-side: every (field, n, d) has at least one variant, one is marked
+    selected, pinning and unpinning work, and bad indices are rejected."""
+    for field in (bg.BG_FIELD_C128, bg.BG_FIELD_FP):
+        for n in range(3, 15):
+            for d in range(1, 11):
+                vs = bg.bg_variants(field, n, d)
+                assert vs, (field, n, d)
+                assert sum(v["selected"] for v in vs) == 1
+                for v in vs:
+                    assert v["lanes"] * v["comps_per_lane"] >= d or v["generic"]
+    vs = bg.bg_variants(bg.BG_FIELD_FP, 8, 6)
+    last = vs[-1]["index"]
+    bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, last)
+    assert [v["selected"] for v in bg.bg_variants(bg.BG_FIELD_FP, 8, 6)][-1] == 1
+    bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, -1)
+    with pytest.raises(bg.BGError):
+        bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, 10**6)
+    assert bg.lib().bg_variants(7, 8, 6, None, 0) == bg.BG_EINVAL
+    assert bg.lib().bg_variants(bg.BG_FIELD_FP, 20, 6, None, 0) == bg.BG_EDOMAIN
