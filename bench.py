@@ -19,6 +19,7 @@ integer multiply-add issue.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -124,9 +125,10 @@ def run_workload(kind: str, steps: int, warmup: int):
     n, d = w["n"], w["d"]
     npts = len(w["k"])
     # the library's autotuner picks the kernel variant for this (field, n, d)
-    # on synthetic inputs of the same shape, before anything is timed
+    # on synthetic inputs of the same shape and size, before anything is timed
+    # (same size, so every launch of the chosen kernel in a trace is alike)
     field = bg.BG_FIELD_FP if w["field"] == "fp" else bg.BG_FIELD_C128
-    chosen, tuned = bg.bg_autotune(field, n, d, w["p"] if w["field"] == "fp" else 0, npts=1 << 18, reps=5)
+    chosen, tuned = bg.bg_autotune(field, n, d, w["p"] if w["field"] == "fp" else 0, npts=npts, reps=5)
     if w["field"] == "fp":
         tk = torch.from_numpy(I.to_soa(w["k"]).view(np.int32)).to(dev)
         te = torch.from_numpy(I.to_soa(w["eps"]).view(np.int32)).to(dev)
@@ -162,6 +164,246 @@ def run_workload(kind: str, steps: int, warmup: int):
     }
 
 
+# ----------------------------------------------------------------------------
+# batched form: 88 (field, n, d) groups in one call
+# ----------------------------------------------------------------------------
+
+HBM_PEAK_TBS = 8.0
+
+
+def _gen_group_soa(g):
+    """Worker: one group's inputs in the C-ABI layout (host)."""
+    import numpy as np
+    from paper_2502_07060_amd import inputs as I
+    k, e = I.group_inputs(g)
+    if g["field"] == "fp":
+        return I.to_soa(k.astype(np.uint32)), I.to_soa(e.astype(np.uint32))
+    return I.to_soa(k.astype(np.complex128)), I.to_soa(e.astype(np.complex128))
+
+
+def _gen_workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def group_roofline_ms(field: str, n: int, d: int, npts: int) -> float:
+    """max(HBM time, ALU time) of one group at the peaks used above."""
+    s = 16 if field == "c128" else 4
+    nbytes = npts * ((2 * n - 1) * d * s + s + 1)
+    W = work_per_amplitude(n, d) * npts
+    t_alu = 8 * W / (FP64_PEAK_TFLOPS * 1e12) if field == "c128" else W / (INT_MAD_PEAK_TOPS * 1e12)
+    return 1e3 * max(nbytes / (HBM_PEAK_TBS * 1e12), t_alu)
+
+
+def run_batched(steps: int, warmup: int):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor, as_completed
+
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    p = I.DEFAULT_PRIME
+    groups = [g for g in I.batched_groups() if g["npts"] > 0]
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    tens = {}
+    with ProcessPoolExecutor(max_workers=_gen_workers(), mp_context=mp.get_context("spawn")) as ex:
+        order = sorted(range(len(groups)), key=lambda i: -groups[i]["npts"])
+        futs = {ex.submit(_gen_group_soa, groups[i]): i for i in order}
+        for fu in as_completed(futs):
+            i = futs[fu]
+            ks, es = fu.result()
+            g = groups[i]
+            if g["field"] == "fp":
+                tk = torch.from_numpy(ks.view(np.int32)).to(dev)
+                te = torch.from_numpy(es.view(np.int32)).to(dev)
+                out = torch.empty(g["npts"], dtype=torch.int32, device=dev)
+            else:
+                tk = torch.from_numpy(ks).to(dev)
+                te = torch.from_numpy(es).to(dev)
+                out = torch.empty(g["npts"], dtype=torch.complex128, device=dev)
+            st = torch.full((g["npts"],), 9, dtype=torch.uint8, device=dev)
+            tens[i] = (tk, te, out, st)
+    t_gen = time.perf_counter() - t_gen
+    # the autotuner picks each (field, n, d) group's kernel variant
+    t_tune = time.perf_counter()
+    for g in groups:
+        field = bg.BG_FIELD_FP if g["field"] == "fp" else bg.BG_FIELD_C128
+        bg.bg_autotune(field, g["n"], g["d"], p if g["field"] == "fp" else 0,
+                       npts=min(max(g["npts"], 4096), 1 << 18), reps=3)
+    t_tune = time.perf_counter() - t_tune
+    descs = [bg.make_group(*tens[i], p=p) for i in range(len(groups))]
+    total = sum(g["npts"] for g in groups)
+
+    run = lambda: bg.bg_batch_run(descs)
+    total_ms, launch_ms, wall = time_launches(run, steps, warmup)
+    bad = sum(int((tens[i][3] != 0).sum().item()) for i in range(len(groups)))
+    plan = bg.BatchPlan(descs)
+    try:
+        p_total_ms, p_launch_ms, _ = time_launches(plan.launch, steps, warmup)
+    finally:
+        plan.close()
+    roof_ms = sum(group_roofline_ms(g["field"], g["n"], g["d"], g["npts"]) for g in groups)
+    best = min(launch_ms, p_launch_ms)
+    return {
+        "workload": "88 groups (n 4..14 x d {4,6,8,10} x {complex128, Z_p}), 4*10^6 points, "
+                    "Zipf(1.2) group sizes, seed 4",
+        "value": total / (best * 1e-3), "unit": "amplitudes/s", "npts": total, "groups": len(groups),
+        "ms_batch_run": launch_ms, "ms_graph_plan": p_launch_ms,
+        "roofline": {"bound": "mixed (per group max of HBM and ALU time)", "roofline_ms": roof_ms,
+                     "measured_ms": best, "frac": roof_ms / best},
+        "nonzero_status": bad, "host_generation_s": t_gen, "autotune_s": t_tune,
+    }
+
+
+# ----------------------------------------------------------------------------
+# serving form: Poisson request stream, served vs plain per-request launches
+# ----------------------------------------------------------------------------
+
+SERVE_NS = list(range(4, 15))
+SERVE_DS = [4, 6, 10]
+SERVE_POOL = 65536        # columns of each host input pool (largest request)
+SERVE_DISTINCT = 2048     # distinct points per pool, tiled across its columns
+
+
+def serve_trace(count: int, seed: int = 5):
+    """Request shapes and sizes: field and n, d uniform; size floor(exp(U[0, ln 65536])) in [1, 65536]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    fields = rng.integers(0, 2, size=count)
+    ns = rng.choice(SERVE_NS, size=count)
+    ds = rng.choice(SERVE_DS, size=count)
+    sizes = np.clip(np.floor(np.exp(rng.uniform(0, math.log(SERVE_POOL), size=count))), 1, SERVE_POOL).astype(np.int64)
+    offs = (rng.random(count) * (SERVE_POOL - sizes + 1)).astype(np.int64)
+    gaps = rng.exponential(1.0, size=count)      # unit-rate Poisson gaps, scaled per rate
+    return [dict(field=("c128", "fp")[f], n=int(n), d=int(d), npts=int(m), off=int(o))
+            for f, n, d, m, o in zip(fields, ns, ds, sizes, offs)], np.cumsum(gaps) - gaps[0]
+
+
+def _serve_pool_inputs(key):
+    import numpy as np
+    from paper_2502_07060_amd import inputs as I
+    field, n, d = key
+    g = dict(field=field, n=n, d=d, npts=SERVE_DISTINCT, seed=50_000 + 100 * n + d + (7 if field == "fp" else 0))
+    k, e = I.group_inputs(g)
+    if field == "fp":
+        return I.to_soa(k.astype(np.uint32)).view(np.int32), I.to_soa(e.astype(np.uint32)).view(np.int32)
+    return I.to_soa(k.astype(np.complex128)), I.to_soa(e.astype(np.complex128))
+
+
+def run_served(count: int, fracs=(0.5, 0.7, 0.9), budget_gib: float = 8.0):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    p = I.DEFAULT_PRIME
+    trace, unit_arrivals = serve_trace(count)
+    keys = sorted({(r["field"], r["n"], r["d"]) for r in trace})
+    t_gen = time.perf_counter()
+    pools = {}
+    with ProcessPoolExecutor(max_workers=_gen_workers(), mp_context=mp.get_context("spawn")) as ex:
+        for key, (ks, es) in zip(keys, ex.map(_serve_pool_inputs, keys)):
+            reps = SERVE_POOL // SERVE_DISTINCT
+            dt = torch.int32 if key[0] == "fp" else torch.complex128
+            n, d = key[1], key[2]
+            pk = torch.empty((n, d, SERVE_POOL), dtype=dt, pin_memory=True)
+            pe = torch.empty((n, d, SERVE_POOL), dtype=dt, pin_memory=True)
+            pk.numpy().reshape(n, d, reps, SERVE_DISTINCT)[:] = ks[:, :, None, :]
+            pe.numpy().reshape(n, d, reps, SERVE_DISTINCT)[:] = es[:, :, None, :]
+            pools[key] = (pk, pe)
+    # per-request output slices of two pinned pools
+    tot_c = sum(r["npts"] for r in trace if r["field"] == "c128")
+    tot_f = sum(r["npts"] for r in trace if r["field"] == "fp")
+    out_c = torch.empty(max(tot_c, 1), dtype=torch.complex128, pin_memory=True)
+    out_f = torch.empty(max(tot_f, 1), dtype=torch.int32, pin_memory=True)
+    st_all = torch.empty(max(tot_c + tot_f, 1), dtype=torch.uint8, pin_memory=True)
+    descs = []
+    oc = of = 0
+    for r in trace:
+        pk, pe = pools[(r["field"], r["n"], r["d"])]
+        es = 16 if r["field"] == "c128" else 4
+        m = r["npts"]
+        if r["field"] == "c128":
+            optr = out_c.data_ptr() + oc * es
+            sptr = st_all.data_ptr() + oc
+            oc += m
+        else:
+            optr = out_f.data_ptr() + of * es
+            sptr = st_all.data_ptr() + tot_c + of
+            of += m
+        field = bg.BG_FIELD_FP if r["field"] == "fp" else bg.BG_FIELD_C128
+        descs.append(bg.bg_group(field, r["n"], r["d"], p if r["field"] == "fp" else 0, m, SERVE_POOL,
+                                 pk.data_ptr() + r["off"] * es, pe.data_ptr() + r["off"] * es, optr, sptr))
+    t_gen = time.perf_counter() - t_gen
+    for field, n, d in keys:
+        f = bg.BG_FIELD_FP if field == "fp" else bg.BG_FIELD_C128
+        bg.bg_autotune(f, n, d, p if field == "fp" else 0, npts=1 << 16, reps=3)
+    mean_size = sum(r["npts"] for r in trace) / len(trace)
+    L = bg.lib()
+    budget = int(budget_gib * (1 << 30))
+
+    def replay(plain: bool, rate):
+        """Submits the trace at arrival times unit_arrivals / rate (all at once
+        if rate is None); returns throughput and latency percentiles."""
+        srv = bg.Server(budget, plain=plain)
+        try:
+            ids = []
+            rid = ctypes.c_uint64()
+            t0 = bg.bg_server_now_ns()
+            arr = [0.0] * len(descs) if rate is None else list(unit_arrivals / rate)
+            base = time.perf_counter()
+            for dsc, at in zip(descs, arr):
+                while time.perf_counter() - base < at:
+                    pass
+                rc = L.bg_server_submit(srv._h, ctypes.byref(dsc), ctypes.byref(rid))
+                if rc != bg.BG_OK:
+                    raise bg.BGError(rc, "bg_server_submit")
+                ids.append(rid.value)
+            lat, done_max, shared = [], 0, 0
+            tm = bg.bg_request_times()
+            for i, at in zip(ids, arr):
+                rc = L.bg_server_wait(srv._h, i, -1.0, ctypes.byref(tm))
+                if rc != bg.BG_OK:
+                    raise bg.BGError(rc, "bg_server_wait")
+                lat.append((tm.done_ns - (t0 + at * 1e9)) * 1e-6)
+                done_max = max(done_max, tm.done_ns)
+                shared += tm.batch_requests > 1
+            st = srv.stats()
+        finally:
+            srv.close()
+        lat = np.array(lat)
+        span = (done_max - t0) * 1e-9
+        return {"throughput": sum(r["npts"] for r in trace) / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "launches": st["batches"],
+                "requests_sharing_a_launch": shared, "arena_peak_bytes": st["arena_peak"], "span_s": span}
+
+    replay(False, None)            # warm-up: first touches of pinned pages and kernels
+    plain_sat = replay(True, None)
+    served_sat = replay(False, None)
+    rates = []
+    for fr in fracs:
+        lam = fr * plain_sat["throughput"] / mean_size
+        rates.append({"frac_of_plain_throughput": fr, "requests_per_s": lam,
+                      "served": replay(False, lam), "plain": replay(True, lam)})
+    bad = int((st_all != 0).sum().item())
+    return {
+        "workload": f"{count} requests, Poisson arrivals, sizes floor(exp(U[0, ln 65536])), n 4..14, "
+                    "d {4,6,10}, complex128 or Z_p, seed 5; inputs and outputs in pinned host memory, "
+                    "latency from arrival to results on the host",
+        "mean_request_points": mean_size, "arena_gib": budget_gib,
+        "saturated": {"plain": plain_sat, "served": served_sat,
+                      "served_over_plain": served_sat["throughput"] / plain_sat["throughput"]},
+        "rates": rates, "nonzero_status": bad, "host_setup_s": t_gen,
+    }
+
+
 def calibrate_copy(mib: int):
     if mib <= 0:
         return
@@ -180,7 +422,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6144)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6"], default="both",
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served"], default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one device-to-device copy of MIB MiB: a plain copy "
@@ -193,6 +438,12 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if a.workload == "batched":
+        print(json.dumps(run_batched(a.steps, a.warmup)), flush=True)
+        return
+    if a.workload == "served":
+        print(json.dumps(run_served(a.serve_requests)), flush=True)
+        return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
         calibrate_copy(a.calibrate_copy)
@@ -231,6 +482,10 @@ def main(argv=None):
             "variant": fp_run["variant"],
         },
     }
+    if not a.no_batched:
+        line["batched"] = run_batched(a.steps, a.warmup)
+    if not a.no_served:
+        line["served"] = run_served(a.serve_requests)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline("c8_d4", a.cpu_sample)
         line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 2)

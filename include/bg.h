@@ -147,6 +147,74 @@ int bg_batch_plan_launch(bg_batch_plan* plan, void* hip_stream);
 int bg_batch_plan_destroy(bg_batch_plan* plan);
 
 /*
+ * Serving loop.  A server owns one device arena of hbm_budget_bytes (one
+ * allocation at creation, on the current device), a few streams and one
+ * scheduler thread.  Requests are bg_group records whose four pointers are
+ * HOST memory (pinned memory lets copies overlap kernels): momenta and pols
+ * [n][d][ld] with ld the host leading dimension, out [npts] and status
+ * [npts] (status may be NULL).  The host buffers must stay valid until the
+ * request completes.
+ *
+ * Each request occupies npts (2 n d s + s + 1) bytes of the arena while it
+ * runs (s = 16 complex, 4 F_p; columns padded to 64 points, parts to 256
+ * bytes).  Requests are admitted first come, first served as arena space
+ * and launch slots free up; requests waiting for the same (field, n, d, p)
+ * are merged into one kernel launch over adjacent columns; several launches
+ * are in flight at once on separate streams, their copies overlapping other
+ * launches' kernels.  Every point is computed exactly as by
+ * bg_amplitudes_c128 / bg_amplitudes_fp with the kernel variant selected
+ * for its (field, n, d), so a request's results do not depend on what it
+ * was batched with.
+ *
+ * With flags = BG_SERVER_PLAIN the server runs one request per launch, one at
+ * a time, in arrival order, on one stream (the plain baseline).
+ */
+#define BG_SERVER_PLAIN 1
+typedef struct bg_server bg_server;
+
+typedef struct {
+  int64_t submit_ns;    /* steady-clock times (bg_server_now_ns): submitted,  */
+  int64_t launch_ns;    /* its copies and kernel enqueued,                     */
+  int64_t done_ns;      /* completion seen by the scheduler (results on host)  */
+  int32_t batch_requests;  /* requests that shared its kernel launch          */
+} bg_request_times;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t batches;           /* kernel launches made                          */
+  int64_t points;            /* points of completed requests                  */
+  int64_t queued;            /* requests waiting for admission                */
+  int64_t inflight_batches;
+  int64_t arena_bytes, arena_in_use, arena_peak;
+} bg_server_stats;
+
+/* BG_EINVAL (bad flags, budget < 256 B), BG_ENOMEM (arena allocation
+ * failed), BG_EHIP. */
+int bg_server_create(size_t hbm_budget_bytes, int flags, bg_server** srv);
+
+/* Validates like bg_batch_run (same codes); BG_ENOMEM if the request alone
+ * exceeds the arena, BG_EBUSY if 2^20 requests are already queued.  On
+ * BG_OK *id names the request; npts == 0 completes at once. */
+int bg_server_submit(bg_server* srv, const bg_group* request, uint64_t* id);
+
+/* 1 if done, 0 if not yet, BG_EINVAL for an unknown id. */
+int bg_server_poll(bg_server* srv, uint64_t id);
+
+/* Blocks until the request is done (timeout_s < 0: no limit), fills times
+ * (may be NULL) and forgets the id.  Returns the request's result code
+ * (BG_OK, or BG_EHIP if a copy or launch failed), BG_EBUSY on timeout (the id
+ * stays valid), BG_EINVAL for an unknown id. */
+int bg_server_wait(bg_server* srv, uint64_t id, double timeout_s, bg_request_times* times);
+
+int bg_server_get_stats(bg_server* srv, bg_server_stats* out);
+
+/* The clock of bg_request_times, in nanoseconds. */
+int64_t bg_server_now_ns(void);
+
+/* Finishes every submitted request, then frees the arena and the streams. */
+int bg_server_destroy(bg_server* srv);
+
+/*
  * Kernel variants (tuning interface).  Several kernels may be compiled for one
  * (field, n, d): lanes per point, components per lane, per-point tables in
  * registers or LDS, or the runtime-n kernel.  The library picks one by

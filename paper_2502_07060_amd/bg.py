@@ -44,6 +44,13 @@ _SIGNATURES = {
     "bg_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bg_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "bg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]),
+    "bg_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "bg_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p]),
+    "bg_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_server_now_ns": (ctypes.c_int64, []),
+    "bg_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "bg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "bg_version": (ctypes.c_int, []),
 }
@@ -257,6 +264,111 @@ class BatchPlan:
         if self._h:
             lib().bg_batch_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------
+# serving loop
+# ----------------------------------------------------------------------------
+
+BG_SERVER_PLAIN = 1
+
+
+class bg_request_times(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64),
+                ("batch_requests", ctypes.c_int32)]
+
+
+class bg_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "batches", "points", "queued",
+                                               "inflight_batches", "arena_bytes", "arena_in_use", "arena_peak")]
+
+
+def _host_ptr(x):
+    """Address of a host buffer: a CPU torch tensor or a numpy array (contiguous)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        if x.is_cuda or not x.is_contiguous():
+            raise ValueError("server requests take contiguous host tensors")
+        return x.data_ptr()
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("server requests take contiguous host arrays")
+    return x.ctypes.data
+
+
+def _is_complex(x):
+    return str(x.dtype).endswith("complex128")
+
+
+def bg_server_now_ns() -> int:
+    return lib().bg_server_now_ns()
+
+
+class Server:
+    """A serving loop on the current device (bg_server_*).  Requests are host
+    buffers laid out as for bg_amplitudes_*: momenta and pols [n][d][ld],
+    out [npts], status [npts]; pinned torch tensors let copies overlap."""
+
+    def __init__(self, hbm_budget_bytes: int, plain: bool = False):
+        self._h = ctypes.c_void_p()
+        rc = lib().bg_server_create(int(hbm_budget_bytes), BG_SERVER_PLAIN if plain else 0, ctypes.byref(self._h))
+        if rc != BG_OK:
+            raise BGError(rc, "bg_server_create")
+        self._live = {}
+
+    def submit(self, momenta, pols, out, status=None, p: int = 0, npts=None) -> int:
+        n, d, ld = momenta.shape
+        field = BG_FIELD_C128 if _is_complex(momenta) else BG_FIELD_FP
+        g = bg_group(field, n, d, p if field == BG_FIELD_FP else 0, ld if npts is None else int(npts), ld,
+                     _host_ptr(momenta), _host_ptr(pols), _host_ptr(out), _host_ptr(status))
+        rid = ctypes.c_uint64()
+        rc = lib().bg_server_submit(self._h, ctypes.byref(g), ctypes.byref(rid))
+        if rc != BG_OK:
+            raise BGError(rc, "bg_server_submit")
+        self._live[rid.value] = (momenta, pols, out, status)   # the buffers outlive the request
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        rc = lib().bg_server_poll(self._h, rid)
+        if rc < 0:
+            raise BGError(rc, "bg_server_poll")
+        return rc == 1
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        """Waits for a request; returns its times (dict) and forgets it."""
+        t = bg_request_times()
+        rc = lib().bg_server_wait(self._h, rid, float(timeout), ctypes.byref(t))
+        if rc == BG_EBUSY:
+            raise TimeoutError(f"request {rid} not done after {timeout} s")
+        self._live.pop(rid, None)
+        if rc != BG_OK:
+            raise BGError(rc, "bg_server_wait")
+        return {k: getattr(t, k) for k, _ in bg_request_times._fields_}
+
+    def stats(self) -> dict:
+        s = bg_server_stats()
+        rc = lib().bg_server_get_stats(self._h, ctypes.byref(s))
+        if rc != BG_OK:
+            raise BGError(rc, "bg_server_get_stats")
+        return {k: getattr(s, k) for k, _ in bg_server_stats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            lib().bg_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -19,6 +19,15 @@
 
 namespace bg {
 
+int validate_group(const bg_group& g) {
+  if (g.field != BG_FIELD_C128 && g.field != BG_FIELD_FP) return BG_EINVAL;
+  if (g.n < 3 || g.n > BG_MAX_N || g.d < 1 || g.d > BG_MAX_D) return BG_EDOMAIN;
+  if (g.npts < 0) return BG_EINVAL;
+  if (g.field == BG_FIELD_FP && (g.p < 3 || g.p >= 0x80000000u || !is_prime_u32(g.p))) return BG_ENOTPRIME;
+  if (g.npts > 0 && (g.ld < g.npts || !g.momenta || !g.pols || !g.out)) return BG_EINVAL;
+  return BG_OK;
+}
+
 namespace {
 
 constexpr int kStreams = 4;
@@ -31,15 +40,6 @@ int64_t work_per_point(int field, int n, int d) {
   return field == FIELD_C128 ? 2 * W : W;  // a complex multiply-add costs about two F_p ones
 }
 
-int validate(const bg_group& g) {
-  if (g.field != BG_FIELD_C128 && g.field != BG_FIELD_FP) return BG_EINVAL;
-  if (g.n < 3 || g.n > BG_MAX_N || g.d < 1 || g.d > BG_MAX_D) return BG_EDOMAIN;
-  if (g.npts < 0) return BG_EINVAL;
-  if (g.field == BG_FIELD_FP && (g.p < 3 || g.p >= 0x80000000u || !is_prime_u32(g.p))) return BG_ENOTPRIME;
-  if (g.npts > 0 && (g.ld < g.npts || !g.momenta || !g.pols || !g.out)) return BG_EINVAL;
-  return BG_OK;
-}
-
 struct Prepared {
   LaunchSpec spec;
   int64_t cost;
@@ -48,7 +48,7 @@ struct Prepared {
 int prepare_all(const bg_group* groups, int ngroups, std::vector<Prepared>& out) {
   if (ngroups < 0 || (ngroups > 0 && !groups)) return BG_EINVAL;
   for (int i = 0; i < ngroups; ++i) {
-    const int rc = validate(groups[i]);
+    const int rc = validate_group(groups[i]);
     if (rc != BG_OK) return rc;
   }
   out.clear();

@@ -8,6 +8,7 @@
 
 #include <vector>
 
+#include "bg.h"
 #include "bg_kernel.h"
 
 namespace bg {
@@ -44,6 +45,8 @@ bool is_prime_u32(uint32_t n);
 int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
             void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec);
 int enqueue(LaunchSpec& spec, hipStream_t stream);
+// argument checks of one bg_group (field, ranges, prime, pointers)
+int validate_group(const bg_group& g);
 
 struct Registrar {
   explicit Registrar(const Variant& v) { registry().push_back(v); }

@@ -112,3 +112,21 @@ def test_variant_listing_and_selection():
         bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, 10**6)
     assert bg.lib().bg_variants(7, 8, 6, None, 0) == bg.BG_EINVAL
     assert bg.lib().bg_variants(bg.BG_FIELD_FP, 20, 6, None, 0) == bg.BG_EDOMAIN
+
+
+def test_server_argument_checks_without_gpu():
+    """Server entry points reject bad handles and flags before touching the GPU."""
+    L = bg.lib()
+    h = ctypes.c_void_p()
+    assert L.bg_server_create(0, 0, ctypes.byref(h)) == bg.BG_EINVAL
+    assert L.bg_server_create(1 << 20, 2, ctypes.byref(h)) == bg.BG_EINVAL
+    assert L.bg_server_create(1 << 20, 0, None) == bg.BG_EINVAL
+    rid = ctypes.c_uint64()
+    g = bg.bg_group(bg.BG_FIELD_FP, 8, 6, 2147483629, 10, 10, 0x1000, 0x1000, 0x1000, None)
+    assert L.bg_server_submit(None, ctypes.byref(g), ctypes.byref(rid)) == bg.BG_EINVAL
+    assert L.bg_server_poll(None, 1) == bg.BG_EINVAL
+    assert L.bg_server_wait(None, 1, 0.0, None) == bg.BG_EINVAL
+    assert L.bg_server_get_stats(None, None) == bg.BG_EINVAL
+    assert L.bg_server_destroy(None) == bg.BG_OK
+    t0 = bg.bg_server_now_ns()
+    assert bg.bg_server_now_ns() >= t0
