@@ -6,7 +6,7 @@
 #include <mutex>
 
 #include "bg.h"
-#include "bg_generic.h"
+#include "bg_wide.h"
 #include "bg_registry.h"
 
 namespace bg {
@@ -114,6 +114,13 @@ static int pinned(int field, int n, int d) {
 bool is_pinned(int field, int n, int d) { return pinned(field, n, d) >= 0; }
 
 const Variant* default_variant(int field, int n, int d);
+static int max_lds_per_block();
+
+// a wide kernel keeps at least 512 lanes (8 waves) busy per CU at this N
+static bool best_fills(const Variant* v, int N) {
+  const unsigned per = v->lds_per_point ? v->lds_per_point(N) : 0;
+  return per && (long)(max_lds_per_block() / per) * v->L >= 512;
+}
 
 const Variant* choose_variant(int field, int n, int d) {
   const int idx = pinned(field, n, d);
@@ -139,18 +146,24 @@ const Variant* default_variant(int field, int n, int d) {
       best = &v;
   }
   if (best) return best;
+  // runtime-n kernels: the smallest DMAX that covers d; among those the
+  // lane-sharing (wide) form whose resident points fill a CU with the fewest
+  // lanes per point, else the one-point-per-lane form
+  int dmax = 0;
+  for (const Variant& v : registry())
+    if (v.generic && v.field == field && v.DL >= d && (!dmax || v.DL < dmax)) dmax = v.DL;
   for (const Variant& v : registry()) {
-    if (!v.generic || v.field != field || v.DL < d) continue;
-    if (!best || v.DL < best->DL) best = &v;
+    if (!v.generic || v.field != field || v.DL != dmax || v.L == 1) continue;
+    const unsigned per = v.lds_per_point ? v.lds_per_point(N) : 0;
+    const long resident = per ? (long)(max_lds_per_block() / per) * v.L : 0;
+    const bool fills = resident >= 512;
+    if (!best || (fills && (best->L > v.L || !best_fills(best, N))) || (!fills && !best_fills(best, N) && v.L > best->L))
+      best = &v;
   }
-  return best;
-}
-
-static size_t generic_bytes_per_point(int field, int N, int dmax) {
-  const size_t e = field == FIELD_FP ? 4 : 16;
-  const int ncur = N * (N + 1) / 2 - 1;
-  const int nprop = std::max(0, N * (N - 1) / 2 - 1);
-  return (size_t)(ncur + 2 * N + 1) * dmax * e + (size_t)2 * ncur * e + (size_t)nprop * e;
+  if (best) return best;
+  for (const Variant& v : registry())
+    if (v.generic && v.field == field && v.DL == dmax) return &v;
+  return nullptr;
 }
 
 static int max_lds_per_block() {
@@ -181,6 +194,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.fp = fp;
   spec.fn = v->fn;
   spec.generic = v->generic;
+  spec.lanes = v->L;
   spec.N = n - 1;
   if (!v->generic) {
     const int64_t threads = npts * v->L;
@@ -191,10 +205,24 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
     spec.shmem = 0;
     return BG_OK;
   }
-  const size_t per = generic_bytes_per_point(field, n - 1, v->DL);
+  const size_t per = v->lds_per_point ? v->lds_per_point(n - 1) : 0;
   const int maxlds = max_lds_per_block();
-  int P = (int)std::min<size_t>(256, (size_t)maxlds / per);
-  if (P >= 64) P = P / 64 * 64;
+  if (per == 0 || per > (size_t)maxlds) return BG_ENOTIMPL;
+  int P;  // points per block
+  if (v->L == 1) {
+    P = (int)std::min<size_t>(256, (size_t)maxlds / per);
+    if (P >= 64) P = P / 64 * 64;
+  } else {
+    // G lanes per point: the block size whose blocks hold the most points per CU
+    const int pmax = std::min<int>(256 / v->L, (int)((size_t)maxlds / per));
+    P = 1;
+    long bestres = 0;
+    for (int c = 1; c <= pmax; ++c) {
+      const long blocks = std::min<long>((long)maxlds / ((long)c * (long)per), 2048 / ((long)c * v->L));
+      const long res = blocks * c;
+      if (res > bestres || (res == bestres && c > P)) { bestres = res; P = c; }
+    }
+  }
   if (P < 1) return BG_ENOTIMPL;
   const size_t shmem = per * P;
   if (shmem > 65536) {
@@ -205,7 +233,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   const int64_t blocks = (npts + P - 1) / P;
   if (blocks > 0x7FFFFFFF) return BG_EINVAL;
   spec.grid = (unsigned)blocks;
-  spec.block = (unsigned)P;
+  spec.block = (unsigned)(P * v->L);
   spec.shmem = (unsigned)shmem;
   return BG_OK;
 }

@@ -60,7 +60,7 @@ int prepare_all(const bg_group* groups, int ngroups, std::vector<Prepared>& out)
     if (g.field == BG_FIELD_FP) k = make_fp_const(g.p);
     const int rc = prepare(g.field, g.n, g.d, g.npts, g.ld, g.momenta, g.pols, g.out, g.status, k, pr.spec);
     if (rc != BG_OK) return rc;
-    pr.cost = g.npts * work_per_point(g.field, g.n, g.d) * (pr.spec.generic ? 6 : 1);
+    pr.cost = g.npts * work_per_point(g.field, g.n, g.d) * (pr.spec.generic ? (pr.spec.lanes == 1 ? 6 : 2) : 1);
     out.push_back(pr);
   }
   std::stable_sort(out.begin(), out.end(), [](const Prepared& a, const Prepared& b) { return a.cost > b.cost; });

@@ -17,14 +17,15 @@ enum : int { FIELD_C128 = 0, FIELD_FP = 1 };
 
 struct Variant {
   int field;
-  int N;          // n - 1 (0 for the runtime-n generic kernel)
-  int DL;         // components per lane (DMAX for the generic kernel)
-  int L;          // lanes per point
-  int block;      // threads per block
+  int N;          // n - 1 (0 for the runtime-n kernels)
+  int DL;         // components per lane (DMAX for the runtime-n kernels)
+  int L;          // lanes per point (runtime-n: 1 = one point per lane, G = lanes sharing a point)
+  int block;      // threads per block (0: chosen at launch)
   bool generic;   // runtime-n kernel with LDS tables
   bool lds_tables;  // register kernel with per-point tables in LDS
   int waves;        // minimum waves per SIMD the register allocation allows
   const void* fn;
+  unsigned (*lds_per_point)(int N) = nullptr;  // runtime-n kernels: LDS bytes per point
 };
 
 std::vector<Variant>& registry();
@@ -35,7 +36,8 @@ bool is_pinned(int field, int n, int d);
 struct LaunchSpec {
   const void* fn = nullptr;
   unsigned grid = 0, block = 0, shmem = 0;
-  bool generic = false;
+  bool generic = false;  // runtime-n kernel (takes N as a second argument)
+  int lanes = 1;         // lanes per point
   int N = 0;
   LaunchArgs args;
 };
@@ -51,6 +53,16 @@ int validate_group(const bg_group& g);
 struct Registrar {
   explicit Registrar(const Variant& v) { registry().push_back(v); }
 };
+
+// LDS bytes per point of a runtime-n kernel (one instantiation per layout)
+template <class Layout>
+unsigned generic_lds_bytes(int N) {
+  return (unsigned)Layout::bytes_per_point(N);
+}
+template <class Layout>
+unsigned wide_lds_bytes(int N) {
+  return Layout::offsets(N).total;
+}
 
 }  // namespace bg
 
@@ -72,5 +84,16 @@ struct Registrar {
   template __global__ void bg_generic_kernel<FLD<DMAX_, 1>, DMAX_>(LaunchArgs, int);            \
   static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
       FIELDTAG, 0, DMAX_, 1, 0, true, true, 1,                                                  \
-      reinterpret_cast<const void*>(&bg_generic_kernel<FLD<DMAX_, 1>, DMAX_>)});                \
+      reinterpret_cast<const void*>(&bg_generic_kernel<FLD<DMAX_, 1>, DMAX_>),                  \
+      &generic_lds_bytes<GenericLayout<FLD<DMAX_, 1>, DMAX_>>});                                \
+  }
+
+// runtime-n kernel with G lanes sharing each point's tables in LDS
+#define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_)                                              \
+  namespace bg {                                                                                \
+  template __global__ void bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_>(LaunchArgs, int);           \
+  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
+      FIELDTAG, 0, DMAX_, G_, 0, true, true, 1,                                                 \
+      reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_>),                 \
+      &wide_lds_bytes<WideLayout<FLD<DMAX_, 1>, DMAX_, G_>>});                                 \
   }

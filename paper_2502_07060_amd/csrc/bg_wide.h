@@ -1,0 +1,402 @@
+// Berends-Giele recursion for large n (paper Sec. 2.2) with a group of G
+// lanes per phase-space point and the point's current table shared in LDS.
+//
+// One lane per point (bg_generic.h) needs the whole table per lane, so only a
+// handful of points fit a CU at n >= 9.  Here the G lanes of a group split the
+// work of one point instead.  Ranges of one length m depend only on shorter
+// ranges, so the recursion advances length by length; within a length, the
+// work items are (range S = [i..j], cut c) for i <= c < j:
+//
+//   the three-gluon split A = [i..c] | B = [c+1..j],
+//   every four-gluon split [i..c] | [c+1..t] | [t+1..j] (c < t < j),
+//   the two adjacent-pair terms of the four-gluon vertex that pair J_A or
+//   J_B with the stored -D/2 of the other part (see bg_kernel.h),
+//
+// each item summing its contribution to K'(S) over the full d components in
+// one lane (no cross-lane dot products).  With G < 32 the cuts c and
+// i + j - 1 - c form one item, which evens out the number of four-gluon
+// splits per item.  Items are dealt to the lanes in rounds of G; after each
+// round the lane that owns S (lane i) adds the round's partial sums of S, in
+// cut order, to its accumulator, so the result does not depend on timing.
+// The owner then finishes S: J(S) = 2 K'(S) / P_S^2 into the LDS table, or
+// at the root M = 2 eps_n . K'.
+//
+// Same identities as the register kernel; the sum over splits is taken in
+// item order instead of split order, which changes only the rounding of the
+// complex path.  F_p propagator inverses: each lane inverts its share of the
+// denominators with one batched inversion and one Fermat power.
+#pragma once
+
+#include "bg_generic.h"
+
+namespace bg {
+
+template <class Fld, int DMAX, int G>
+struct WideLayout {
+  using E = typename Fld::E;
+  using S = typename Fld::S;
+  using A = typename Fld::A;
+  static constexpr bool kFp = Fld::exact;
+  struct Off {
+    unsigned J, mom, epsn, nDh, nc, inv, part, pscal, flags, total;
+  };
+  __host__ __device__ static int ncur(int N) { return N * (N + 1) / 2 - 1; }
+  __host__ __device__ static unsigned up16(size_t x) { return (unsigned)((x + 15) / 16 * 16); }
+  // per-point LDS offsets (bytes): current table by range index, momenta
+  // (F_p: prefix sums Q_0..Q_N; complex: primed k'_0..k'_{N-1}), eps_n,
+  // scalars by range index, one partial K and scalar per lane, flags
+  __host__ __device__ static Off offsets(int N) {
+    Off o{};
+    unsigned x = 0;
+    o.J = x;      x += up16((size_t)ncur(N) * DMAX * sizeof(E));
+    o.mom = x;    x += up16((size_t)(N + 1) * DMAX * sizeof(E));
+    o.epsn = x;   x += up16((size_t)DMAX * sizeof(E));
+    o.nDh = x;    x += up16((size_t)ncur(N) * sizeof(S));
+    o.nc = x;     x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
+    o.inv = x;    x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
+    o.part = x;   x += up16((size_t)G * DMAX * sizeof(A));
+    o.pscal = x;  x += up16((size_t)G * sizeof(S));
+    o.flags = x;  x += 16;
+    o.total = x;
+    return o;
+  }
+};
+
+template <class Fld, int DMAX, int G>
+struct WideRecursion {
+  using E = typename Fld::E;
+  using S = typename Fld::S;
+  using A = typename Fld::A;
+  using Lay = WideLayout<Fld, DMAX, G>;
+  using Rec = Recursion<Fld, 2, DMAX, 1>;  // scalar helpers
+  static constexpr bool kFp = Fld::exact;
+  static constexpr bool kPairs = G < 32;
+
+  E* Jt;
+  E* Mt;
+  E* En;
+  S* nDht;
+  S* nct;
+  S* invt;
+  A* part;
+  S* pscal;
+  unsigned* flags;
+  int N, g;
+
+  __device__ WideRecursion(char* base, int N_, int g_) : N(N_), g(g_) {
+    const auto o = Lay::offsets(N);
+    Jt = reinterpret_cast<E*>(base + o.J);
+    Mt = reinterpret_cast<E*>(base + o.mom);
+    En = reinterpret_cast<E*>(base + o.epsn);
+    nDht = reinterpret_cast<S*>(base + o.nDh);
+    nct = reinterpret_cast<S*>(base + o.nc);
+    invt = reinterpret_cast<S*>(base + o.inv);
+    part = reinterpret_cast<A*>(base + o.part);
+    pscal = reinterpret_cast<S*>(base + o.pscal);
+    flags = reinterpret_cast<unsigned*>(base + o.flags);
+  }
+
+  __device__ __forceinline__ int rid(int i, int j) const { return range_idx(N, i, j); }
+  __device__ __forceinline__ void loadJ(int r, E (&x)[DMAX]) const {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) x[c] = Jt[r * DMAX + c];
+  }
+  __device__ __forceinline__ void loadM(int l, E (&x)[DMAX]) const {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) x[c] = Mt[l * DMAX + c];
+  }
+  // primed P_S (F_p: from prefix sums; complex: left-to-right sum of k')
+  __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
+    if constexpr (kFp) {
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(Mt[(j + 1) * DMAX + c], Mt[i * DMAX + c]);
+      P[0] = F.prime0(P[0]);
+    } else {
+      loadM(i, P);
+      for (int l = i + 1; l <= j; ++l) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], Mt[l * DMAX + c]);
+      }
+    }
+  }
+
+  // ---- loads: eps into the table, momenta, eps_n; F_p prefix sums --------
+  __device__ void load(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad) {
+    const int rows = (2 * N + 1) * DMAX;  // eps_0..eps_N, k_0..k_{N-1}
+    for (int r = g; r < rows; r += G) {
+      const int which = r / DMAX, c = r % DMAX;
+      if (which <= N) {
+        const E e = Loader<Fld>::get(a, a.pols, which, c, q, bad);
+        if (which < N) Jt[rid(which, which) * DMAX + c] = e;
+        else En[c] = e;
+      } else {
+        const int l = which - N - 1;
+        E k = Loader<Fld>::get(a, a.momenta, l, c, q, bad);
+        if constexpr (kFp) {
+          Mt[(l + 1) * DMAX + c] = k;  // raw k_l, summed below
+        } else {
+          if (c == 0) k = F.prime0(k);
+          Mt[l * DMAX + c] = k;
+        }
+      }
+    }
+    if (g == 0) *flags = 0u;
+    __syncthreads();
+    if constexpr (kFp) {
+      if (g < DMAX) {  // prefix sums, one component per lane
+        E acc{};
+        Mt[g] = acc;
+        for (int l = 0; l < N; ++l) {
+          acc = F.eadd(acc, Mt[(l + 1) * DMAX + g]);
+          Mt[(l + 1) * DMAX + g] = acc;
+        }
+      }
+      __syncthreads();
+      for (int l = g; l < N; l += G) {  // nc(l) = P_l . eps_l
+        E Pp[DMAX], e[DMAX];
+        primedP(F, l, l, Pp);
+        loadJ(rid(l, l), e);
+        nct[rid(l, l)] = F.ndot(Pp, e);
+      }
+    }
+  }
+
+  // ---- F_p: -P_S^2 for every 2 <= |S| <= N-1, inverted per lane ---------
+  __device__ void inverses(const Fld& F, bool& singular) {
+    if constexpr (kFp) {
+      const int np = N * (N - 1) / 2 - 1;  // ranges of length 2..N-1 have indices N .. N+np-1
+      int32_t acc = F.k.one;
+      bool any = false;
+      for (int r = g; r < np; r += G) {  // forward: y into invt, prefix products into nDht
+        const int id = N + r;
+        int len = 2, base = 0;
+        while (r >= base + (N - len + 1)) { base += N - len + 1; ++len; }
+        const int i = r - base;
+        E Pp[DMAX], Pu[DMAX];
+        primedP(F, i, i + len - 1, Pp);
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+        Pu[0] = F.prime0(Pp[0]);
+        int32_t y = F.ndot(Pp, Pu);
+        if (y == 0) { singular = true; y = F.k.one; }
+        acc = any ? fp_mul(acc, y, F.k) : y;
+        any = true;
+        invt[id] = y;
+        nDht[id] = acc;
+      }
+      if (any) {
+        int32_t t = fp_pow(acc, (uint32_t)(F.k.p - 2), F.k);
+        t = fp_mul(t, -F.k.two, F.k);  // 1/y = -1/P^2 -> 2/P^2
+        int last = g;
+        while (last + G < np) last += G;
+        for (int r = last; r >= g; r -= G) {
+          const int id = N + r;
+          const int32_t y = invt[id];
+          invt[id] = r > g ? fp_mul(t, nDht[id - G], F.k) : t;
+          t = fp_mul(t, y, F.k);
+        }
+      }
+    }
+  }
+
+  // ---- one work item: contributions of cut c to K'(S), S = [i..j] ---------
+  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], A (&K)[DMAX], S& nDs) const {
+    E JA[DMAX], JB[DMAX];
+    loadJ(rid(i, c), JA);
+    loadJ(rid(c + 1, j), JB);
+    const S nDm = F.ndot_u(JA, JB);  // -(J_A . J_B)
+    if constexpr (kFp) {
+      E Qt[DMAX];
+      loadM(c + 1, Qt);
+      const S nc2 = F.ndot_sub(Pp, JA, nct[rid(i, c)]);       // -(P_B . J_A)
+      const S nc3 = F.ndot_sub(Pp, JB, nct[rid(c + 1, j)]);   // -(P_A . J_B)
+      F.axpy(K, F.sneg(nDm), Qt);
+      F.axpy(K, F.sneg(nc2), JB);
+      F.axpy(K, nc3, JA);
+      F.fold(K);
+    } else {
+      E PA[DMAX], PB[DMAX], v[DMAX];
+      primedP(F, i, c, PA);
+      primedP(F, c + 1, j, PB);
+      const S n2 = F.ndot(PB, JA);
+      const S n3 = F.ndot(PA, JB);
+#pragma unroll
+      for (int x = 0; x < DMAX; ++x) v[x] = F.esub(PA[x], PB[x]);
+      v[0] = F.prime0(v[0]);  // P_A - P_B
+      F.axpy(K, cplx{-0.5 * nDm.re, -0.5 * nDm.im}, v);
+      F.axpy(K, F.sneg(n2), JB);
+      F.axpy(K, n3, JA);
+    }
+    nDs = Rec::accumulate_scalar(F, nDs, nDm);
+    // adjacent-pair terms of the four-gluon vertex that involve this cut
+    if (c >= i + 1) F.axpy(K, nDht[rid(i, c)], JB);
+    if (c <= j - 2) F.axpy(K, nDht[rid(c + 1, j)], JA);
+    F.fold(K);
+    // four-gluon splits [i..c] | [c+1..t] | [t+1..j]
+    int cnt = 0;
+    for (int t = c + 1; t < j; ++t) {
+      E JM[DMAX], JC[DMAX];
+      loadJ(rid(c + 1, t), JM);
+      loadJ(rid(t + 1, j), JC);
+      const S ne = F.ndot_u(JA, JC);
+      F.axpy(K, F.sneg(ne), JM);
+      if (++cnt == 5) { F.fold(K); cnt = 0; }
+    }
+    F.fold(K);
+  }
+
+  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result) {
+    uint32_t bad = 0;
+    bool singular = false;
+    load(F, a, q, bad);
+    inverses(F, singular);
+    __syncthreads();
+
+    for (int m = 2; m <= N; ++m) {
+      const int nr = N - m + 1;                 // ranges of length m: i = 0 .. nr-1
+      const int per = kPairs ? m / 2 : m - 1;   // items per range
+      const int items = nr * per;
+      const bool own = g < nr;
+      const int oi = g, oj = g + m - 1;         // the range this lane owns
+      A K[DMAX];
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) K[c] = F.azero();
+      S nDsum = F.szero();
+      for (int k0 = 0; k0 < items; k0 += G) {
+        const int k = k0 + g;
+        if (k < items) {
+          const int i = k / per, u = k % per, j = i + m - 1;
+          E Pp[DMAX];
+          if constexpr (kFp) primedP(F, i, j, Pp);
+          A Kp[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) Kp[c] = F.azero();
+          S nDs = F.szero();
+          cut(F, i, j, i + u, Pp, Kp, nDs);
+          if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) part[g * DMAX + c] = Kp[c];
+          pscal[g] = nDs;
+        }
+        __syncthreads();
+        if (own) {
+          // this round's items of the owned range, in item (= cut) order
+          const int lo = max(k0, oi * per), hi = min(k0 + G, (oi + 1) * per);
+          for (int kk = lo; kk < hi; ++kk) {
+            const int slot = kk - k0;
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) K[c] = add_acc(F, K[c], part[slot * DMAX + c]);
+            nDsum = Rec::accumulate_scalar(F, nDsum, pscal[slot]);
+          }
+        }
+        __syncthreads();
+      }
+      if (own) {
+        const bool root = (m == N);
+        const S nDhS = Rec::half_scalar(F, nDsum);
+        E Pp[DMAX];
+        primedP(F, oi, oj, Pp);
+        if constexpr (kFp) {
+          // -Dh(S) (Q_i + Q_{j+1})
+          E Qi[DMAX], Qj[DMAX];
+          loadM(oi, Qi);
+          loadM(oj + 1, Qj);
+          F.axpy(K, nDhS, Qi);
+          F.axpy(K, nDhS, Qj);
+          F.fold(K);
+        }
+        if (!root) {
+          const int id = rid(oi, oj);
+          nDht[id] = nDhS;
+          S inv2;
+          if constexpr (kFp) {
+            inv2 = invt[id];
+          } else {
+            E Pu[DMAX];
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+            Pu[0] = F.prime0(Pp[0]);
+            const S y = F.ndot(Pp, Pu);
+            inv2 = Rec::c_inverse_times(y, -2.0, singular);
+          }
+          E Jn[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            Jn[c] = F.mul(F.finish(K[c]), inv2);
+            Jt[id * DMAX + c] = Jn[c];
+          }
+          if constexpr (kFp) nct[id] = F.ndot(Pp, Jn);
+        } else {
+          E Kf[DMAX], en[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            Kf[c] = F.finish(K[c]);
+            en[c] = En[c];
+          }
+          result = F.ndot_u(en, Kf);
+        }
+      }
+      __syncthreads();
+    }
+    // per-point flags: bit 0 bad residue (F_p), bit 1 singular
+    unsigned fl = singular ? 2u : 0u;
+    if constexpr (kFp) fl |= bad >= (uint32_t)F.k.p ? 1u : 0u;
+    if (fl) atomicOr(flags, fl);
+    __syncthreads();
+  }
+
+  // K + partial (F_p: both below 2^61 + 2^32 after their folds, refolded)
+  __device__ __forceinline__ static A add_acc(const Fld& F, A x, A y) {
+    if constexpr (kFp) return fp_fold(x + y, F.k);
+    else return cadd(x, y);
+  }
+};
+
+// G lanes per point, blockDim.x / G points per block, LDS from the host
+// (points per block x WideLayout::offsets(N).total bytes).
+template <class Fld, int DMAX, int G>
+__global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
+  extern __shared__ __align__(16) char lds[];
+  using Lay = WideLayout<Fld, DMAX, G>;
+  const int g = (int)(threadIdx.x % G);
+  const int pb = (int)(threadIdx.x / G);
+  const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / G) + pb;
+  const bool valid = q0 < a.npts;
+  const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
+  WideRecursion<Fld, DMAX, G> W(lds + (size_t)pb * Lay::offsets(N).total, N, g);
+  typename Fld::S res;
+  if constexpr (Fld::exact) {
+    Fld F(a.fp, 0);
+    W.run(F, a, q, res);
+    if (valid && g == 0) {
+      const unsigned fl = *W.flags;
+      const uint8_t st = (fl & 1u) ? PT_BADRESIDUE : ((fl & 2u) ? PT_SINGULAR : PT_OK);
+      uint32_t outv = 0xFFFFFFFFu;
+      if (st == PT_OK) {
+        int32_t m = fp_mul(res, a.fp.r4, a.fp);
+        m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
+        outv = fp_to_canonical(m, a.fp);
+      }
+      static_cast<uint32_t*>(a.out)[q] = outv;
+      if (a.status) a.status[q] = st;
+    }
+  } else {
+    Fld F(0);
+    W.run(F, a, q, res);
+    if (valid && g == 0) {
+      const bool sing = (*W.flags & 2u) != 0;
+      double2 o;
+      if (sing) {
+        o.x = __builtin_nan("");
+        o.y = __builtin_nan("");
+      } else {
+        o.x = -2.0 * res.re;
+        o.y = -2.0 * res.im;
+      }
+      static_cast<double2*>(a.out)[q] = o;
+      if (a.status) a.status[q] = sing ? PT_SINGULAR : PT_OK;
+    }
+  }
+}
+
+}  // namespace bg

@@ -51,3 +51,31 @@ def test_every_c128_variant(torch_dev, n, d):
             bgtest.check_c(v_g, v_o, k, e, label=f"c128 n={n} d={d} variant {v}")
     finally:
         bg.bg_select_variant(bg.BG_FIELD_C128, n, d, -1)
+
+
+@pytest.mark.parametrize("n", [9, 11, 14])
+@pytest.mark.parametrize("d", [4, 6, 10])
+def test_every_runtime_n_variant_large_n(torch_dev, n, d):
+    """The runtime-n kernels (one point per lane, or a group of lanes per
+    point) at multiplicities with no register instantiation, both fields."""
+    m = 24 if n <= 11 else 10
+    k, e = I.generic_fp(900 + 10 * n + d, n, d, m)
+    rng = np.random.default_rng(n + 100 * d + 7)
+    k = np.concatenate([k.astype(np.int64), rng.integers(0, P, size=(5, n, d))])
+    e = np.concatenate([e.astype(np.int64), rng.integers(0, P, size=(5, n, d))])
+    st_o, v_o = bgtest.oracle_fp(k, e, P)
+    kc, ec = I.generic_c128(950 + 10 * n + d, n, d, m)
+    stc_o, vc_o = bgtest.oracle_c(kc, ec)
+    try:
+        for v in bg.bg_variants(bg.BG_FIELD_FP, n, d):
+            bg.bg_select_variant(bg.BG_FIELD_FP, n, d, v["index"])
+            st_g, v_g = gpu_fp(torch_dev, k, e, P)
+            assert_fp_equal(st_g, v_g, st_o, v_o, f"fp n={n} d={d} variant {v}")
+        for v in bg.bg_variants(bg.BG_FIELD_C128, n, d):
+            bg.bg_select_variant(bg.BG_FIELD_C128, n, d, v["index"])
+            st_g, v_g = gpu_c(torch_dev, kc, ec)
+            assert np.array_equal(st_g, stc_o)
+            bgtest.check_c(v_g, vc_o, kc, ec, label=f"c128 n={n} d={d} variant {v}")
+    finally:
+        bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1)
+        bg.bg_select_variant(bg.BG_FIELD_C128, n, d, -1)
