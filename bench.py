@@ -247,6 +247,17 @@ def run_batched(steps: int, warmup: int):
         plan.close()
     roof_ms = sum(group_roofline_ms(g["field"], g["n"], g["d"], g["npts"]) for g in groups)
     best = min(launch_ms, p_launch_ms)
+    # each group alone (same kernels), to show where the time goes
+    per_group = []
+    for i, g in enumerate(groups):
+        one = [descs[i]]
+        _, ms, _ = time_launches(lambda: bg.bg_batch_run(one), 3, 1)
+        field = bg.BG_FIELD_FP if g["field"] == "fp" else bg.BG_FIELD_C128
+        sel = next(v for v in bg.bg_variants(field, g["n"], g["d"]) if v["selected"])
+        per_group.append({"field": g["field"], "n": g["n"], "d": g["d"], "npts": g["npts"], "ms": ms,
+                          "roofline_ms": group_roofline_ms(g["field"], g["n"], g["d"], g["npts"]),
+                          "variant": {k: sel[k] for k in ("lanes", "comps_per_lane", "lds_tables", "generic")}})
+    per_group.sort(key=lambda r: -r["ms"])
     return {
         "workload": "88 groups (n 4..14 x d {4,6,8,10} x {complex128, Z_p}), 4*10^6 points, "
                     "Zipf(1.2) group sizes, seed 4",
@@ -255,6 +266,7 @@ def run_batched(steps: int, warmup: int):
         "roofline": {"bound": "mixed (per group max of HBM and ALU time)", "roofline_ms": roof_ms,
                      "measured_ms": best, "frac": roof_ms / best},
         "nonzero_status": bad, "host_generation_s": t_gen, "autotune_s": t_tune,
+        "sum_of_groups_alone_ms": sum(r["ms"] for r in per_group), "slowest_groups": per_group[:12],
     }
 
 

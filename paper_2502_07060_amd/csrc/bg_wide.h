@@ -62,6 +62,15 @@ struct WideLayout {
   }
 };
 
+// The G lanes of a group lie in one wavefront (G divides 64), so a group needs
+// no workgroup barrier: waiting for this wave's LDS operations and keeping
+// the compiler from moving LDS accesses across the point is enough.
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <class Fld, int DMAX, int G>
 struct WideRecursion {
   using E = typename Fld::E;
@@ -141,7 +150,7 @@ struct WideRecursion {
       }
     }
     if (g == 0) *flags = 0u;
-    __syncthreads();
+    group_sync();
     if constexpr (kFp) {
       if (g < DMAX) {  // prefix sums, one component per lane
         E acc{};
@@ -151,7 +160,7 @@ struct WideRecursion {
           Mt[(l + 1) * DMAX + g] = acc;
         }
       }
-      __syncthreads();
+      group_sync();
       for (int l = g; l < N; l += G) {  // nc(l) = P_l . eps_l
         E Pp[DMAX], e[DMAX];
         primedP(F, l, l, Pp);
@@ -234,6 +243,7 @@ struct WideRecursion {
     F.fold(K);
     // four-gluon splits [i..c] | [c+1..t] | [t+1..j]
     int cnt = 0;
+#pragma unroll 2
     for (int t = c + 1; t < j; ++t) {
       E JM[DMAX], JC[DMAX];
       loadJ(rid(c + 1, t), JM);
@@ -250,7 +260,7 @@ struct WideRecursion {
     bool singular = false;
     load(F, a, q, bad);
     inverses(F, singular);
-    __syncthreads();
+    group_sync();
 
     for (int m = 2; m <= N; ++m) {
       const int nr = N - m + 1;                 // ranges of length m: i = 0 .. nr-1
@@ -278,7 +288,7 @@ struct WideRecursion {
           for (int c = 0; c < DMAX; ++c) part[g * DMAX + c] = Kp[c];
           pscal[g] = nDs;
         }
-        __syncthreads();
+        group_sync();
         if (own) {
           // this round's items of the owned range, in item (= cut) order
           const int lo = max(k0, oi * per), hi = min(k0 + G, (oi + 1) * per);
@@ -289,7 +299,7 @@ struct WideRecursion {
             nDsum = Rec::accumulate_scalar(F, nDsum, pscal[slot]);
           }
         }
-        __syncthreads();
+        group_sync();
       }
       if (own) {
         const bool root = (m == N);
@@ -336,13 +346,13 @@ struct WideRecursion {
           result = F.ndot_u(en, Kf);
         }
       }
-      __syncthreads();
+      group_sync();
     }
     // per-point flags: bit 0 bad residue (F_p), bit 1 singular
     unsigned fl = singular ? 2u : 0u;
     if constexpr (kFp) fl |= bad >= (uint32_t)F.k.p ? 1u : 0u;
     if (fl) atomicOr(flags, fl);
-    __syncthreads();
+    group_sync();
   }
 
   // K + partial (F_p: both below 2^61 + 2^32 after their folds, refolded)
@@ -352,12 +362,13 @@ struct WideRecursion {
   }
 };
 
-// G lanes per point, blockDim.x / G points per block, LDS from the host
+// G lanes per point (G divides 64), blockDim.x / G points per block, LDS from the host
 // (points per block x WideLayout::offsets(N).total bytes).
 template <class Fld, int DMAX, int G>
 __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   extern __shared__ __align__(16) char lds[];
   using Lay = WideLayout<Fld, DMAX, G>;
+  static_assert(G >= 16 && 64 % G == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
   const int g = (int)(threadIdx.x % G);
   const int pb = (int)(threadIdx.x / G);
   const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / G) + pb;
