@@ -73,6 +73,7 @@ FpConst make_fp_const(uint32_t p) {
   k.c64 = balanced(R, p);
   k.one = k.c64;
   k.two = balanced(2 * R, p);
+  k.two32 = balanced(2 * c32, p);  // 2^33 mod p
   k.inv2 = balanced((unsigned __int128)R * ((p + 1) / 2) % p, p);
   const uint64_t R2 = (unsigned __int128)R * R % p;
   k.r4 = balanced((unsigned __int128)R2 * R2 % p, p);

@@ -37,62 +37,76 @@ struct FpField {
   __device__ __forceinline__ S szero() const { return 0; }
   __device__ __forceinline__ A azero() const { return 0; }
 
-  // group-wide sum of a lane partial of `terms` products per lane, then REDC
-  __device__ __forceinline__ S finish_dot(A t, int terms_per_lane) const {
-    if constexpr (L == 1) {
-      if (terms_per_lane > 4) t = fp_fold(t, k);
-    } else {
-      // per-lane partial < 2^61 + 2^32 after one fold, < 2^59 + 2^32 after two
-      if (L * terms_per_lane > 7) {
+  // Accumulator bounds are tracked in "units" of 2^60 at compile time (every
+  // loop here is unrolled): a product of two balanced values is below one
+  // unit, a product with a difference of two balanced values below two; a
+  // folded accumulator is below two units; an int64 holds up to eight.
+  template <int UX>
+  __device__ __forceinline__ void acc_dot(A& t, int& u, const E* x, const E* y) const {
+#pragma unroll
+    for (int c = 0; c < DL; ++c) {
+      if (u + UX > 7) {
         t = fp_fold(t, k);
-        if constexpr (L >= 4) t = fp_fold(t, k);
+        u = 2;
+      }
+      t = mad64(x[c], y[c], t);
+      u += UX;
+    }
+  }
+
+  // group-wide sum of lane partials below u units each, then REDC (which
+  // needs fewer than four units)
+  __device__ __forceinline__ S finish_dot(A t, int u) const {
+    if constexpr (L > 1) {
+      if (L * u > 7) {
+        t = fp_fold(t, k);
+        u = 2;
+        if (L * u > 7) {  // a second fold leaves below 2^59 + 2^33
+          t = fp_fold(t, k);
+          u = 1;
+        }
       }
       t = group_sum<L>(t, [](A a, A b) { return a + b; },
                        [](auto ctrl, A v) { return (A)dpp_u64<decltype(ctrl)::value>((uint64_t)v); });
-      t = fp_fold(t, k);
+      u *= L;
     }
+    if (u > 3) t = fp_fold(t, k);
     return fp_redc2(t, k);
   }
 
-  // -(x.y) for primed x (x' slots already carry the time sign)
+  // -(x.y) for primed x (x' slots already carry the time sign); UX = 2 when
+  // the slots of x are unreduced differences of two balanced values
+  template <int UX = 1>
   __device__ __forceinline__ S ndot(const E* xp, const E* y) const {
     A t = 0;
-#pragma unroll
-    for (int c = 0; c < DL; ++c) {
-      t = mad64(xp[c], y[c], t);
-      if (c == 6) t = fp_fold(t, k);
-    }
-    return finish_dot(t, DL > 7 ? 5 + (DL - 7) : DL);
+    int u = 0;
+    acc_dot<UX>(t, u, xp, y);
+    return finish_dot(t, u);
   }
 
   // -(x.y) for unprimed x: slot 0 is primed on the fly
   __device__ __forceinline__ S ndot_u(const E* x, const E* y) const {
-    A t = mul64(prime0(x[0]), y[0]);
+    E x0[DL];
 #pragma unroll
-    for (int c = 1; c < DL; ++c) {
-      t = mad64(x[c], y[c], t);
-      if (c == 6) t = fp_fold(t, k);
-    }
-    return finish_dot(t, DL > 7 ? 5 + (DL - 7) : DL);
+    for (int c = 0; c < DL; ++c) x0[c] = x[c];
+    x0[0] = prime0(x[0]);
+    return ndot<1>(x0, y);
   }
 
   // -(x.y) - z  (z a balanced Montgomery value, lifted into the product
-  // accumulator by the factor R mod p)
+  // accumulator by the factor R mod p, added once per group on group lane 0)
+  template <int UX = 1>
   __device__ __forceinline__ S ndot_sub(const E* xp, const E* y, S z) const {
     A t = 0;
-#pragma unroll
-    for (int c = 0; c < DL; ++c) {
-      t = mad64(xp[c], y[c], t);
-      if (c == 5) t = fp_fold(t, k);
+    int u = 0;
+    acc_dot<UX>(t, u, xp, y);
+    if (u + 1 > 7) {
+      t = fp_fold(t, k);
+      u = 2;
     }
-    if constexpr (L == 1) {
-      t = mad64(-z, k.c64, t);
-      return fp_redc2(fp_fold(t, k), k);
-    } else {
-      // the scalar is added once per group, on group lane 0
-      t = mad64(time_lane ? -z : 0, k.c64, t);
-      return finish_dot(t, DL + 1 > 7 ? 8 : DL + 1);
-    }
+    if constexpr (L == 1) t = mad64(-z, k.c64, t);
+    else t = mad64(time_lane ? -z : 0, k.c64, t);
+    return finish_dot(t, u + 1);
   }
 
   __device__ __forceinline__ void axpy(A* K, S c, const E* v) const {
@@ -104,6 +118,11 @@ struct FpField {
     for (int i = 0; i < DL; ++i) K[i] = fp_fold(K[i], k);
   }
   __device__ __forceinline__ E finish(A K) const { return fp_redc2(fp_fold(K, k), k); }
+  // finish(K) * c for a c carrying an extra factor 2^-32 (one 32-bit REDC step
+  // instead of a full one before the product)
+  __device__ __forceinline__ E finish_mul32(A K, S c) const {
+    return fp_redc2(mul64(fp_redc1(fp_fold(K, k), k), c), k);
+  }
   __device__ __forceinline__ E mul(E x, S c) const { return fp_mul(x, c, k); }
   __device__ __forceinline__ S smul(S a, S b) const { return fp_mul(a, b, k); }
 };

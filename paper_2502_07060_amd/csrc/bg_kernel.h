@@ -111,9 +111,11 @@ struct Inverses<FpField<DL, L>, NP> {
         if (y[s] == 0) { zero = true; y[s] = F.k.one; }
         pre[s] = s == 0 ? y[0] : fp_mul(pre[s - 1], y[s], F.k);
       }
-      // the factor -2 turns 1/y = -1/P^2 into 2/P^2 for every element
+      // the factor -2 turns 1/y = -1/P^2 into 2/P^2 for every element; the
+      // extra 2^-32 in the constant pairs with the single 32-bit REDC step
+      // that finishes each current (FpField::finish_mul32)
       int32_t t = fp_pow(pre[NP - 1], (uint32_t)(F.k.p - 2), F.k);
-      t = fp_mul(t, -F.k.two, F.k);
+      t = fp_mul(t, -F.k.two32, F.k);
 #pragma unroll
       for (int s = NP - 1; s >= 0; --s) {
         inv.set(s, s == 0 ? t : fp_mul(t, pre[s - 1], F.k));
@@ -275,7 +277,7 @@ struct Recursion {
         constexpr bool root = (i == 0 && j == N - 1);
         E Pp[DL];
         if constexpr (kFp) {
-          primedP<i, j>(F, mom, Pp);
+          lazyP<i, j>(F, mom, Pp);  // unreduced: |slot| <= 2h
         } else {
 #pragma unroll
           for (int c = 0; c < DL; ++c) Pp[c] = col[i][c];
@@ -286,6 +288,7 @@ struct Recursion {
 
         // three-gluon vertex, A = [i..t], B = [t+1..j]
         S nDsum = F.szero();
+        [[maybe_unused]] int64_t nDacc = 0;  // F_p: sum of -(J_A.J_B) * (1/2), unreduced
         [[maybe_unused]] E PA[DL];
         static_for<i, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
@@ -294,8 +297,8 @@ struct Recursion {
           if constexpr (kFp) {
             // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
             // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
-            const S nc2 = F.ndot_sub(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
-            const S nc3 = F.ndot_sub(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
+            const S nc2 = F.template ndot_sub<2>(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
+            const S nc3 = F.template ndot_sub<2>(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
             E Qt[DL];
 #pragma unroll
             for (int c = 0; c < DL; ++c) Qt[c] = Qg(t + 1, c);
@@ -316,21 +319,26 @@ struct Recursion {
             F.axpy(K, F.sneg(n2), J[ib]);
             F.axpy(K, n3, J[ia]);
           }
-          nDsum = accumulate_scalar(F, nDsum, nDm);
+          if constexpr (kFp) {
+            // at most six products below one unit each between folds
+            if constexpr ((t - i) % 6 == 5) nDacc = fp_fold(nDacc, F.k);
+            nDacc = mad64(nDm, F.k.inv2, nDacc);
+          } else {
+            nDsum = accumulate_scalar(F, nDsum, nDm);
+          }
           split_barrier();
         });
-        const S nDhS = half_scalar(F, nDsum);
+        S nDhS;
         if constexpr (kFp) {
-          // -Dh(S) (Q_i + Q_{j+1})
-          E Qi[DL], Qj[DL];
+          nDhS = fp_redc2(fp_fold(nDacc, F.k), F.k);
+          // -Dh(S) (Q_i + Q_{j+1}), the two prefix sums added unreduced (|.| <= 2h)
+          E QQ[DL];
 #pragma unroll
-          for (int c = 0; c < DL; ++c) {
-            Qi[c] = Qg(i, c);
-            Qj[c] = Qg(j + 1, c);
-          }
-          F.axpy(K, nDhS, Qi);
-          F.axpy(K, nDhS, Qj);
+          for (int c = 0; c < DL; ++c) QQ[c] = Qg(i, c) + Qg(j + 1, c);
+          F.axpy(K, nDhS, QQ);
           F.fold(K);
+        } else {
+          nDhS = half_scalar(F, nDsum);
         }
         if constexpr (!root) nDh.set(R::pidx(i, j), nDhS);
 
@@ -371,9 +379,14 @@ struct Recursion {
             inv2 = c_inverse_times(y, -2.0, singular);
           }
           constexpr int id = R::idx(i, j);
+          if constexpr (kFp) {
 #pragma unroll
-          for (int c = 0; c < DL; ++c) J[id][c] = F.mul(F.finish(K[c]), inv2);
-          if constexpr (kFp) nc.set(id, F.ndot(Pp, J[id]));
+            for (int c = 0; c < DL; ++c) J[id][c] = F.finish_mul32(K[c], inv2);
+            nc.set(id, F.template ndot<2>(Pp, J[id]));
+          } else {
+#pragma unroll
+            for (int c = 0; c < DL; ++c) J[id][c] = F.mul(F.finish(K[c]), inv2);
+          }
         } else {
           // a6: returns -(eps_n . K'); the amplitude is M = 2 eps_n . K'
           E Kf[DL];
@@ -398,6 +411,16 @@ struct Recursion {
 #if BG_SPLIT_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
+  }
+
+  // primed P_S = Q_{j+1} - Q_i as plain int32 differences of balanced values
+  // (|slot| <= 2h < 2^31; a product with a balanced value is below 2^61), with
+  // the time slot negated (F_p)
+  template <int i, int j, class Tab>
+  __device__ static __forceinline__ void lazyP(const Fld& F, const Tab& Q, E (&P)[DL]) {
+#pragma unroll
+    for (int c = 0; c < DL; ++c) P[c] = Q.get((j + 1) * DL + c) - Q.get(i * DL + c);
+    P[0] = F.prime0(P[0]);
   }
 
   // primed P_S = Q_{j+1} - Q_i with the time slot negated (F_p)

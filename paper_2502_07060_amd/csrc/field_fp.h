@@ -41,6 +41,7 @@ struct FpConst {
                   // and the factor that lifts a Montgomery value into a product accumulator
   int32_t r4;     // R^4 mod p, balanced   (output fix-up factor)
   int32_t two;    // 2 R mod p, balanced   (the constant 2, Montgomery form)
+  int32_t two32;  // 2^33 mod p, balanced  (2 R 2^-32: the constant 2 with an extra 2^-32)
   int32_t inv2;   // 2^-1 R mod p, balanced (the constant 1/2, Montgomery form)
   int32_t one;    // R mod p (= c64)
 };
@@ -54,6 +55,13 @@ __device__ __forceinline__ int64_t fp_fold(int64_t T, const FpConst& F) {
   int32_t hi = (int32_t)(T >> 32);
   uint32_t lo = (uint32_t)T;
   return mad64(hi, F.c32, (int64_t)lo);
+}
+
+// one 32-bit REDC step: |T| < 2^61 + 2^32  ->  T 2^-32 mod p with
+// |result| < 2^30 + 2^29 + 1 (an int32, not balanced)
+__device__ __forceinline__ int32_t fp_redc1(int64_t T, const FpConst& F) {
+  const int32_t t1 = (int32_t)((uint32_t)T * F.pinv);
+  return (int32_t)(mad64(t1, F.negp, T) >> 32);
 }
 
 // |T| < 2^62  ->  T R^-1 mod p, balanced
