@@ -433,7 +433,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=6144)
+    ap.add_argument("--cpu-sample", type=int, default=600_000,
+                    help="points of c8_d4 for the oracle baseline (a quarter as many for fp8_d6)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -500,7 +501,7 @@ def main(argv=None):
         line["served"] = run_served(a.serve_requests)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline("c8_d4", a.cpu_sample)
-        line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 2)
+        line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 4)
     print(json.dumps(line), flush=True)
 
 
