@@ -42,9 +42,11 @@ struct WideLayout {
   };
   __host__ __device__ static int ncur(int N) { return N * (N + 1) / 2 - 1; }
   __host__ __device__ static unsigned up16(size_t x) { return (unsigned)((x + 15) / 16 * 16); }
-  // per-point LDS offsets (bytes): current table by range index, momenta
-  // (F_p: prefix sums Q_0..Q_N; complex: primed k'_0..k'_{N-1}), eps_n,
-  // scalars by range index, one partial K and scalar per lane, flags
+  // per-point LDS offsets (bytes): current table [range][component], momenta
+  // (F_p: prefix sums Q_0..Q_N; complex: primed k'_0..k'_{N-1}) [leg][component],
+  // eps_n, scalars by range index, one partial K [lane][component] and one
+  // scalar per lane, flags.  A vector is contiguous, so a lane reads it with
+  // wide LDS loads.
   __host__ __device__ static Off offsets(int N) {
     Off o{};
     unsigned x = 0;
@@ -106,6 +108,8 @@ struct WideRecursion {
   }
 
   __device__ __forceinline__ int rid(int i, int j) const { return range_idx(N, i, j); }
+  __device__ __forceinline__ E& Jat(int r, int c) const { return Jt[r * DMAX + c]; }
+  __device__ __forceinline__ E& Mat(int l, int c) const { return Mt[l * DMAX + c]; }
   __device__ __forceinline__ void loadJ(int r, E (&x)[DMAX]) const {
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) x[c] = Jt[r * DMAX + c];
@@ -114,19 +118,25 @@ struct WideRecursion {
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) x[c] = Mt[l * DMAX + c];
   }
-  // primed P_S (F_p: from prefix sums; complex: left-to-right sum of k')
+  // primed P_S (F_p: reduced, from prefix sums; complex: left-to-right sum of k')
   __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
     if constexpr (kFp) {
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(Mt[(j + 1) * DMAX + c], Mt[i * DMAX + c]);
+      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(Mat(j + 1, c), Mat(i, c));
       P[0] = F.prime0(P[0]);
     } else {
       loadM(i, P);
       for (int l = i + 1; l <= j; ++l) {
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], Mt[l * DMAX + c]);
+        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], Mat(l, c));
       }
     }
+  }
+  // F_p: primed P_S as unreduced differences Q_{j+1} - Q_i (|slot| <= 2h)
+  __device__ __forceinline__ void lazyP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) P[c] = Mat(j + 1, c) - Mat(i, c);
+    P[0] = F.prime0(P[0]);
   }
 
   // ---- loads: eps into the table, momenta, eps_n; F_p prefix sums --------
@@ -136,16 +146,16 @@ struct WideRecursion {
       const int which = r / DMAX, c = r % DMAX;
       if (which <= N) {
         const E e = Loader<Fld>::get(a, a.pols, which, c, q, bad);
-        if (which < N) Jt[rid(which, which) * DMAX + c] = e;
+        if (which < N) Jat(rid(which, which), c) = e;
         else En[c] = e;
       } else {
         const int l = which - N - 1;
         E k = Loader<Fld>::get(a, a.momenta, l, c, q, bad);
         if constexpr (kFp) {
-          Mt[(l + 1) * DMAX + c] = k;  // raw k_l, summed below
+          Mat(l + 1, c) = k;  // raw k_l, summed below
         } else {
           if (c == 0) k = F.prime0(k);
-          Mt[l * DMAX + c] = k;
+          Mat(l, c) = k;
         }
       }
     }
@@ -154,18 +164,18 @@ struct WideRecursion {
     if constexpr (kFp) {
       if (g < DMAX) {  // prefix sums, one component per lane
         E acc{};
-        Mt[g] = acc;
+        Mat(0, g) = acc;
         for (int l = 0; l < N; ++l) {
-          acc = F.eadd(acc, Mt[(l + 1) * DMAX + g]);
-          Mt[(l + 1) * DMAX + g] = acc;
+          acc = F.eadd(acc, Mat(l + 1, g));
+          Mat(l + 1, g) = acc;
         }
       }
       group_sync();
       for (int l = g; l < N; l += G) {  // nc(l) = P_l . eps_l
         E Pp[DMAX], e[DMAX];
-        primedP(F, l, l, Pp);
+        lazyP(F, l, l, Pp);
         loadJ(rid(l, l), e);
-        nct[rid(l, l)] = F.ndot(Pp, e);
+        nct[rid(l, l)] = F.template ndot<2>(Pp, e);
       }
     }
   }
@@ -195,7 +205,8 @@ struct WideRecursion {
       }
       if (any) {
         int32_t t = fp_pow(acc, (uint32_t)(F.k.p - 2), F.k);
-        t = fp_mul(t, -F.k.two, F.k);  // 1/y = -1/P^2 -> 2/P^2
+        // 1/y = -1/P^2 -> 2/P^2, with the extra 2^-32 that finish_mul32 expects
+        t = fp_mul(t, -F.k.two32, F.k);
         int last = g;
         while (last + G < np) last += G;
         for (int r = last; r >= g; r -= G) {
@@ -209,20 +220,25 @@ struct WideRecursion {
   }
 
   // ---- one work item: contributions of cut c to K'(S), S = [i..j] ---------
-  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], A (&K)[DMAX], S& nDs) const {
+  // F_p: Pp holds unreduced differences, nDs accumulates -(J_A.J_B) / 2 as an
+  // int64 sum of products; complex: Pp is unused, nDs sums -(J_A.J_B).
+  template <class NDS>
+  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], A (&K)[DMAX], NDS& nDs) const {
     E JA[DMAX], JB[DMAX];
-    loadJ(rid(i, c), JA);
-    loadJ(rid(c + 1, j), JB);
+    const int ra = rid(i, c), rb = rid(c + 1, j);
+    loadJ(ra, JA);
+    loadJ(rb, JB);
     const S nDm = F.ndot_u(JA, JB);  // -(J_A . J_B)
     if constexpr (kFp) {
       E Qt[DMAX];
       loadM(c + 1, Qt);
-      const S nc2 = F.ndot_sub(Pp, JA, nct[rid(i, c)]);       // -(P_B . J_A)
-      const S nc3 = F.ndot_sub(Pp, JB, nct[rid(c + 1, j)]);   // -(P_A . J_B)
+      const S nc2 = F.template ndot_sub<2>(Pp, JA, nct[ra]);   // -(P_B . J_A)
+      const S nc3 = F.template ndot_sub<2>(Pp, JB, nct[rb]);   // -(P_A . J_B)
       F.axpy(K, F.sneg(nDm), Qt);
       F.axpy(K, F.sneg(nc2), JB);
       F.axpy(K, nc3, JA);
       F.fold(K);
+      nDs = mad64(nDm, F.k.inv2, nDs);  // at most two terms per item
     } else {
       E PA[DMAX], PB[DMAX], v[DMAX];
       primedP(F, i, c, PA);
@@ -235,22 +251,31 @@ struct WideRecursion {
       F.axpy(K, cplx{-0.5 * nDm.re, -0.5 * nDm.im}, v);
       F.axpy(K, F.sneg(n2), JB);
       F.axpy(K, n3, JA);
+      nDs = cadd(nDs, nDm);
     }
-    nDs = Rec::accumulate_scalar(F, nDs, nDm);
     // adjacent-pair terms of the four-gluon vertex that involve this cut
-    if (c >= i + 1) F.axpy(K, nDht[rid(i, c)], JB);
-    if (c <= j - 2) F.axpy(K, nDht[rid(c + 1, j)], JA);
+    if (c >= i + 1) F.axpy(K, nDht[ra], JB);
+    if (c <= j - 2) F.axpy(K, nDht[rb], JA);
     F.fold(K);
-    // four-gluon splits [i..c] | [c+1..t] | [t+1..j]
+    // four-gluon splits [i..c] | [c+1..t] | [t+1..j].  Range indices advance
+    // incrementally: with e = (right end - left end) of a range, extending
+    // [c+1..t] to [c+1..t+1] adds N - e, and shrinking [t+1..j] to [t+2..j]
+    // adds e - N (from the index formula of range_idx)
+    int rm = rid(c + 1, c + 1), lm = 0;
+    int rc = rid(c + 2, j), lc = j - c - 2;
     int cnt = 0;
 #pragma unroll 2
     for (int t = c + 1; t < j; ++t) {
       E JM[DMAX], JC[DMAX];
-      loadJ(rid(c + 1, t), JM);
-      loadJ(rid(t + 1, j), JC);
+      loadJ(rm, JM);
+      loadJ(rc, JC);
       const S ne = F.ndot_u(JA, JC);
       F.axpy(K, F.sneg(ne), JM);
       if (++cnt == 5) { F.fold(K); cnt = 0; }
+      rm += N - lm;
+      ++lm;
+      rc += lc - N;
+      --lc;
     }
     F.fold(K);
   }
@@ -277,16 +302,23 @@ struct WideRecursion {
         if (k < items) {
           const int i = k / per, u = k % per, j = i + m - 1;
           E Pp[DMAX];
-          if constexpr (kFp) primedP(F, i, j, Pp);
+          if constexpr (kFp) lazyP(F, i, j, Pp);
           A Kp[DMAX];
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) Kp[c] = F.azero();
-          S nDs = F.szero();
-          cut(F, i, j, i + u, Pp, Kp, nDs);
-          if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+          if constexpr (kFp) {
+            int64_t nDs = 0;
+            cut(F, i, j, i + u, Pp, Kp, nDs);
+            if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+            pscal[g] = fp_redc2(fp_fold(nDs, F.k), F.k);  // -(sum of J_A.J_B) / 2
+          } else {
+            S nDs = F.szero();
+            cut(F, i, j, i + u, Pp, Kp, nDs);
+            if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+            pscal[g] = nDs;
+          }
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) part[g * DMAX + c] = Kp[c];
-          pscal[g] = nDs;
         }
         group_sync();
         if (own) {
@@ -303,39 +335,46 @@ struct WideRecursion {
       }
       if (own) {
         const bool root = (m == N);
-        const S nDhS = Rec::half_scalar(F, nDsum);
+        S nDhS;
         E Pp[DMAX];
-        primedP(F, oi, oj, Pp);
         if constexpr (kFp) {
-          // -Dh(S) (Q_i + Q_{j+1})
-          E Qi[DMAX], Qj[DMAX];
-          loadM(oi, Qi);
-          loadM(oj + 1, Qj);
-          F.axpy(K, nDhS, Qi);
-          F.axpy(K, nDhS, Qj);
+          nDhS = nDsum;  // the items' sums already carry the factor 1/2
+          lazyP(F, oi, oj, Pp);
+          // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
+          E QQ[DMAX];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) QQ[c] = Mat(oi, c) + Mat(oj + 1, c);
+          F.axpy(K, nDhS, QQ);
           F.fold(K);
+        } else {
+          nDhS = Rec::half_scalar(F, nDsum);
+          primedP(F, oi, oj, Pp);
         }
         if (!root) {
           const int id = rid(oi, oj);
           nDht[id] = nDhS;
-          S inv2;
+          E Jn[DMAX];
           if constexpr (kFp) {
-            inv2 = invt[id];
+            const S inv2 = invt[id];
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) {
+              Jn[c] = F.finish_mul32(K[c], inv2);
+              Jat(id, c) = Jn[c];
+            }
+            nct[id] = F.template ndot<2>(Pp, Jn);
           } else {
             E Pu[DMAX];
 #pragma unroll
             for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
             Pu[0] = F.prime0(Pp[0]);
             const S y = F.ndot(Pp, Pu);
-            inv2 = Rec::c_inverse_times(y, -2.0, singular);
-          }
-          E Jn[DMAX];
+            const S inv2 = Rec::c_inverse_times(y, -2.0, singular);
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) {
-            Jn[c] = F.mul(F.finish(K[c]), inv2);
-            Jt[id * DMAX + c] = Jn[c];
+            for (int c = 0; c < DMAX; ++c) {
+              Jn[c] = F.mul(F.finish(K[c]), inv2);
+              Jat(id, c) = Jn[c];
+            }
           }
-          if constexpr (kFp) nct[id] = F.ndot(Pp, Jn);
         } else {
           E Kf[DMAX], en[DMAX];
 #pragma unroll
