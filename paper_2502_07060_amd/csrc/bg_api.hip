@@ -77,6 +77,9 @@ FpConst make_fp_const(uint32_t p) {
   k.inv2 = balanced((unsigned __int128)R * ((p + 1) / 2) % p, p);
   const uint64_t R2 = (unsigned __int128)R * R % p;
   k.r4 = balanced((unsigned __int128)R2 * R2 % p, p);
+  // 2^-32 mod p = (2^32 mod p)^(p-2)
+  const uint64_t inv32 = powmod(c32, p - 2, p);
+  k.r4s = balanced((unsigned __int128)((unsigned __int128)R2 * R2 % p) * inv32 % p, p);
   return k;
 }
 

@@ -37,76 +37,96 @@ struct FpField {
   __device__ __forceinline__ S szero() const { return 0; }
   __device__ __forceinline__ A azero() const { return 0; }
 
-  // Accumulator bounds are tracked in "units" of 2^60 at compile time (every
-  // loop here is unrolled): a product of two balanced values is below one
-  // unit, a product with a difference of two balanced values below two; a
-  // folded accumulator is below two units; an int64 holds up to eight.
+  // Accumulator bounds are tracked at compile time (every loop here is
+  // unrolled) in half-units of 2^59; an int64 holds 16.  A product of two
+  // balanced values (|v| <= h < 2^30) is below 2; with one factor an
+  // unreduced difference of two balanced values (< 2^31), below 4; with one
+  // factor a lazily reduced scalar (|s| < 1.5 2^30 + 1, from one 32-bit REDC
+  // step), below 3 (plus 2^30, negligible against the 2^59 kept spare); a
+  // folded accumulator is below 4.
+  static constexpr int kMaxU = 15;
+
   template <int UX>
   __device__ __forceinline__ void acc_dot(A& t, int& u, const E* x, const E* y) const {
 #pragma unroll
     for (int c = 0; c < DL; ++c) {
-      if (u + UX > 7) {
+      if (u + UX > kMaxU) {
         t = fp_fold(t, k);
-        u = 2;
+        u = 4;
       }
       t = mad64(x[c], y[c], t);
       u += UX;
     }
   }
 
-  // group-wide sum of lane partials below u units each, then REDC (which
-  // needs fewer than four units)
+  // group-wide sum of lane partials below u half-units each, then either a
+  // full REDC2 (input below 8, balanced result) or, LAZY, one 32-bit REDC
+  // step (input folded, result |s| < 1.5 2^30 + 1) for scalars that only
+  // multiply balanced vectors.  A lazy result is the REDC2 one times 2^32 mod
+  // p; a caller uses lazy scalars for every term of an accumulator, so the
+  // whole accumulator carries the same factor, removed once when it is
+  // finished.
+  template <bool LAZY>
   __device__ __forceinline__ S finish_dot(A t, int u) const {
     if constexpr (L > 1) {
-      if (L * u > 7) {
+      if (L * u > kMaxU) {
         t = fp_fold(t, k);
-        u = 2;
-        if (L * u > 7) {  // a second fold leaves below 2^59 + 2^33
+        u = 4;
+        if (L * u > kMaxU) {  // a second fold leaves below 2^59 + 2^33
           t = fp_fold(t, k);
-          u = 1;
+          u = 2;
         }
       }
       t = group_sum<L>(t, [](A a, A b) { return a + b; },
                        [](auto ctrl, A v) { return (A)dpp_u64<decltype(ctrl)::value>((uint64_t)v); });
       u *= L;
     }
-    if (u > 3) t = fp_fold(t, k);
-    return fp_redc2(t, k);
+    if constexpr (LAZY) {
+      if (u > 4) t = fp_fold(t, k);
+      return fp_redc1(t, k);
+    } else {
+      if (u > 7) t = fp_fold(t, k);
+      return fp_redc2(t, k);
+    }
   }
 
-  // -(x.y) for primed x (x' slots already carry the time sign); UX = 2 when
-  // the slots of x are unreduced differences of two balanced values
-  template <int UX = 1>
+  // -(x.y) for primed x (x' slots already carry the time sign); UX = 2 for
+  // balanced slots of x, 4 when they are unreduced differences
+  template <int UX = 2, bool LAZY = false>
   __device__ __forceinline__ S ndot(const E* xp, const E* y) const {
     A t = 0;
     int u = 0;
     acc_dot<UX>(t, u, xp, y);
-    return finish_dot(t, u);
+    return finish_dot<LAZY>(t, u);
   }
 
-  // -(x.y) for unprimed x: slot 0 is primed on the fly
+  // -(x.y) for unprimed balanced x: slot 0 is primed on the fly
+  template <bool LAZY = false>
   __device__ __forceinline__ S ndot_u(const E* x, const E* y) const {
     E x0[DL];
 #pragma unroll
     for (int c = 0; c < DL; ++c) x0[c] = x[c];
     x0[0] = prime0(x[0]);
-    return ndot<1>(x0, y);
+    return ndot<2, LAZY>(x0, y);
   }
 
-  // -(x.y) - z  (z a balanced Montgomery value, lifted into the product
-  // accumulator by the factor R mod p, added once per group on group lane 0)
-  template <int UX = 1>
+  // -(x.y) - z  (z lifted into the product accumulator, added once per group
+  // on group lane 0).  UZ = 2: z balanced, lifted by R mod p; UZ = 3: z a
+  // lazily reduced scalar (which carries an extra 2^32), lifted by 2^32 mod p
+  template <int UX = 2, int UZ = 2, bool LAZY = false>
   __device__ __forceinline__ S ndot_sub(const E* xp, const E* y, S z) const {
+    static_assert(UZ == 2 || UZ == 3, "z is balanced or lazily reduced");
     A t = 0;
     int u = 0;
     acc_dot<UX>(t, u, xp, y);
-    if (u + 1 > 7) {
+    if (u + UZ > kMaxU) {
       t = fp_fold(t, k);
-      u = 2;
+      u = 4;
     }
-    if constexpr (L == 1) t = mad64(-z, k.c64, t);
-    else t = mad64(time_lane ? -z : 0, k.c64, t);
-    return finish_dot(t, u + 1);
+    const int32_t lift = UZ == 3 ? k.c32 : k.c64;
+    if constexpr (L == 1) t = mad64(-z, lift, t);
+    else t = mad64(time_lane ? -z : 0, lift, t);
+    return finish_dot<LAZY>(t, u + UZ);
   }
 
   __device__ __forceinline__ void axpy(A* K, S c, const E* v) const {
@@ -179,18 +199,21 @@ struct C128Field {
     }
     return t;
   }
+  template <int UX = 2, bool LAZY = false>
   __device__ __forceinline__ S ndot(const E* xp, const E* y) const {
     cplx t = cmul(xp[0], y[0]);
 #pragma unroll
     for (int c = 1; c < DL; ++c) t = cmad(xp[c], y[c], t);
     return finish_dot(t);
   }
+  template <bool LAZY = false>
   __device__ __forceinline__ S ndot_u(const E* x, const E* y) const {
     cplx t = cmul(prime0(x[0]), y[0]);
 #pragma unroll
     for (int c = 1; c < DL; ++c) t = cmad(x[c], y[c], t);
     return finish_dot(t);
   }
+  template <int UX = 2, int UZ = 2, bool LAZY = false>
   __device__ __forceinline__ S ndot_sub(const E* xp, const E* y, S z) const {
     return csub(ndot(xp, y), z);
   }

@@ -111,11 +111,13 @@ struct Inverses<FpField<DL, L>, NP> {
         if (y[s] == 0) { zero = true; y[s] = F.k.one; }
         pre[s] = s == 0 ? y[0] : fp_mul(pre[s - 1], y[s], F.k);
       }
-      // the factor -2 turns 1/y = -1/P^2 into 2/P^2 for every element; the
-      // extra 2^-32 in the constant pairs with the single 32-bit REDC step
-      // that finishes each current (FpField::finish_mul32)
+      // the factor -2 turns 1/y = -1/P^2 into 2/P^2 for every element.  It
+      // is applied as the plain residue 2 (the constant 2 times R^-1), which
+      // removes both the 2^32 that lazily reduced scalars leave in the current
+      // accumulators and the 2^-32 of the single 32-bit REDC step that
+      // finishes each current (FpField::finish_mul32)
       int32_t t = fp_pow(pre[NP - 1], (uint32_t)(F.k.p - 2), F.k);
-      t = fp_mul(t, -F.k.two32, F.k);
+      t = fp_mul(t, -2, F.k);
 #pragma unroll
       for (int s = NP - 1; s >= 0; --s) {
         inv.set(s, s == 0 ? t : fp_mul(t, pre[s - 1], F.k));
@@ -223,7 +225,7 @@ struct Recursion {
       }
       k[0] = F.prime0(k[0]);
       if constexpr (kFp) {
-        nc.set(R::idx(l, l), F.ndot(k, J[R::idx(l, l)]));
+        nc.set(R::idx(l, l), F.template ndot<2, true>(k, J[R::idx(l, l)]));  // lazily reduced
         k[0] = F.prime0(k[0]);
 #pragma unroll
         for (int c = 0; c < DL; ++c) mom.set((l + 1) * DL + c, F.eadd(Qg(l, c), k[c]));
@@ -293,12 +295,14 @@ struct Recursion {
         static_for<i, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
           constexpr int ia = R::idx(i, t), ib = R::idx(t + 1, j);
-          const S nDm = F.ndot_u(J[ia], J[ib]);            // -(J_A.J_B)
+          // -(J_A.J_B); F_p: lazily reduced (it only multiplies balanced values)
+          const S nDm = F.template ndot_u<kFp>(J[ia], J[ib]);
           if constexpr (kFp) {
             // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
             // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
-            const S nc2 = F.template ndot_sub<2>(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
-            const S nc3 = F.template ndot_sub<2>(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
+            // lazy P_S slots, lazy stored P_X.J_X, lazily reduced results
+            const S nc2 = F.template ndot_sub<4, 3, true>(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
+            const S nc3 = F.template ndot_sub<4, 3, true>(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
             E Qt[DL];
 #pragma unroll
             for (int c = 0; c < DL; ++c) Qt[c] = Qg(t + 1, c);
@@ -320,8 +324,9 @@ struct Recursion {
             F.axpy(K, n3, J[ia]);
           }
           if constexpr (kFp) {
-            // at most six products below one unit each between folds
-            if constexpr ((t - i) % 6 == 5) nDacc = fp_fold(nDacc, F.k);
+            // products below 3 half-units (lazy nDm times balanced 1/2): fold
+            // before every third one after the first three
+            if constexpr (t > i && (t - i) % 3 == 0) nDacc = fp_fold(nDacc, F.k);
             nDacc = mad64(nDm, F.k.inv2, nDacc);
           } else {
             nDsum = accumulate_scalar(F, nDsum, nDm);
@@ -347,10 +352,11 @@ struct Recursion {
           constexpr int s1 = decltype(sc)::value;
           static_for<s1 + 1, j>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
-            const S ne = F.ndot_u(J[R::idx(i, s1)], J[R::idx(t + 1, j)]);
+            const S ne = F.template ndot_u<kFp>(J[R::idx(i, s1)], J[R::idx(t + 1, j)]);  // F_p: lazy
             F.axpy(K, F.sneg(ne), J[R::idx(s1 + 1, t)]);
             constexpr int qn = v4_index<i, j>(s1, t);
-            if constexpr (qn % 5 == 4) F.fold(K);
+            // F_p: lazy scalars give products below 3 half-units: fold every third
+            if constexpr (kFp ? (qn % 3 == 2) : (qn % 5 == 4)) F.fold(K);
             split_barrier();
           });
         });
@@ -382,7 +388,7 @@ struct Recursion {
           if constexpr (kFp) {
 #pragma unroll
             for (int c = 0; c < DL; ++c) J[id][c] = F.finish_mul32(K[c], inv2);
-            nc.set(id, F.template ndot<2>(Pp, J[id]));
+            nc.set(id, F.template ndot<4, true>(Pp, J[id]));  // lazily reduced
           } else {
 #pragma unroll
             for (int c = 0; c < DL; ++c) J[id][c] = F.mul(F.finish(K[c]), inv2);
@@ -486,9 +492,10 @@ void bg_recursion_kernel(LaunchArgs a) {
       uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
       uint32_t outv = 0xFFFFFFFFu;
       if (st == PT_OK) {
-        // res = -(eps_n . K') in Montgomery form of a value scaled by R^-4;
-        // M = 2 eps_n . K' = res * (-2), times R^4 to undo the input scaling.
-        int32_t m = fp_mul(res, a.fp.r4, a.fp);      // -(eps_n . K') * R^3 ... unscaled
+        // res = -(eps_n . K') in Montgomery form of a value scaled by R^-4,
+        // times the 2^32 that the root accumulator carries; M = 2 eps_n . K'
+        // = res * (-2), times R^4 2^-32 to undo both scalings.
+        int32_t m = fp_mul(res, a.fp.r4s, a.fp);
         m = fp_sub(0, fp_add(m, m, a.fp), a.fp);     // * (-2)
         outv = fp_to_canonical(m, a.fp);
       }

@@ -175,7 +175,7 @@ struct WideRecursion {
         E Pp[DMAX], e[DMAX];
         lazyP(F, l, l, Pp);
         loadJ(rid(l, l), e);
-        nct[rid(l, l)] = F.template ndot<2>(Pp, e);
+        nct[rid(l, l)] = F.template ndot<4>(Pp, e);
       }
     }
   }
@@ -232,8 +232,8 @@ struct WideRecursion {
     if constexpr (kFp) {
       E Qt[DMAX];
       loadM(c + 1, Qt);
-      const S nc2 = F.template ndot_sub<2>(Pp, JA, nct[ra]);   // -(P_B . J_A)
-      const S nc3 = F.template ndot_sub<2>(Pp, JB, nct[rb]);   // -(P_A . J_B)
+      const S nc2 = F.template ndot_sub<4>(Pp, JA, nct[ra]);   // -(P_B . J_A)
+      const S nc3 = F.template ndot_sub<4>(Pp, JB, nct[rb]);   // -(P_A . J_B)
       F.axpy(K, F.sneg(nDm), Qt);
       F.axpy(K, F.sneg(nc2), JB);
       F.axpy(K, nc3, JA);
@@ -361,7 +361,7 @@ struct WideRecursion {
               Jn[c] = F.finish_mul32(K[c], inv2);
               Jat(id, c) = Jn[c];
             }
-            nct[id] = F.template ndot<2>(Pp, Jn);
+            nct[id] = F.template ndot<4>(Pp, Jn);
           } else {
             E Pu[DMAX];
 #pragma unroll

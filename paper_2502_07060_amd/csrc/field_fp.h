@@ -40,6 +40,8 @@ struct FpConst {
   int32_t c64;    // 2^64 mod p = R mod p, balanced: the constant 1 in Montgomery form,
                   // and the factor that lifts a Montgomery value into a product accumulator
   int32_t r4;     // R^4 mod p, balanced   (output fix-up factor)
+  int32_t r4s;    // R^4 2^-32 mod p, balanced (output fix-up of the register kernel, whose
+                  // accumulators carry the extra 2^32 of lazily reduced scalars)
   int32_t two;    // 2 R mod p, balanced   (the constant 2, Montgomery form)
   int32_t two32;  // 2^33 mod p, balanced  (2 R 2^-32: the constant 2 with an extra 2^-32)
   int32_t inv2;   // 2^-1 R mod p, balanced (the constant 1/2, Montgomery form)
