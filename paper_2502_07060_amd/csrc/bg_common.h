@@ -47,11 +47,17 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// the two halves move separately and are reassembled as a register pair (an
+// OR of shifted halves would be turned into two 64-bit additions downstream)
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-  uint32_t lo = dpp_u32<CTRL>((uint32_t)v);
-  uint32_t hi = dpp_u32<CTRL>((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
+  const u32x2 x = __builtin_bit_cast(u32x2, v);
+  u32x2 r;
+  r.x = dpp_u32<CTRL>(x.x);
+  r.y = dpp_u32<CTRL>(x.y);
+  return __builtin_bit_cast(uint64_t, r);
 }
 
 template <int CTRL>

@@ -24,8 +24,14 @@ struct FpField {
   static constexpr bool exact = true;
   FpConst k;
   bool time_lane;  // group lane 0: slot 0 is mu = 0
+  // the factor that lifts a subtracted scalar z into a product accumulator,
+  // negated, on group lane 0 only (z is added once per group): by R for a
+  // balanced z, by 2^32 for a lazily reduced one
+  int32_t zlift64, zlift32;
 
-  __device__ FpField(const FpConst& c, int s) : k(c), time_lane(s == 0) {}
+  __device__ FpField(const FpConst& c, int s)
+      : k(c), time_lane(s == 0),
+        zlift64((L == 1 || s == 0) ? -c.c64 : 0), zlift32((L == 1 || s == 0) ? -c.c32 : 0) {}
 
   __device__ __forceinline__ E prime0(E x) const {
     if constexpr (L == 1) return -x;
@@ -123,9 +129,7 @@ struct FpField {
       t = fp_fold(t, k);
       u = 4;
     }
-    const int32_t lift = UZ == 3 ? k.c32 : k.c64;
-    if constexpr (L == 1) t = mad64(-z, lift, t);
-    else t = mad64(time_lane ? -z : 0, lift, t);
+    t = mad64(z, UZ == 3 ? zlift32 : zlift64, t);
     return finish_dot<LAZY>(t, u + UZ);
   }
 

@@ -52,11 +52,14 @@ __device__ __forceinline__ int64_t mul64(int32_t a, int32_t b) { return (int64_t
 
 __device__ __forceinline__ int64_t mad64(int32_t a, int32_t b, int64_t c) { return (int64_t)a * (int64_t)b + c; }
 
-// T congruent, |result| < 2^31 h + 2^32
+// T congruent, |result| < 2^31 h + 2^32.  Formed as T + hi c32 (modulo 2^64)
+// with hi then taken off the high word: one multiply-add into T itself and
+// one 32-bit subtraction, no zero-extended copy of lo.
 __device__ __forceinline__ int64_t fp_fold(int64_t T, const FpConst& F) {
-  int32_t hi = (int32_t)(T >> 32);
-  uint32_t lo = (uint32_t)T;
-  return mad64(hi, F.c32, (int64_t)lo);
+  const int32_t hi = (int32_t)(T >> 32);
+  u32x2 r = __builtin_bit_cast(u32x2, (uint64_t)T + (uint64_t)mul64(hi, F.c32));
+  r.y -= (uint32_t)hi;
+  return (int64_t)__builtin_bit_cast(uint64_t, r);
 }
 
 // one 32-bit REDC step: |T| < 2^61 + 2^32  ->  T 2^-32 mod p with
