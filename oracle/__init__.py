@@ -16,6 +16,8 @@ bg            the recursion itself (paper Sec. 2.2, the current recursion and
               the 3-/4-gluon vertices), memoised over contiguous sub-ranges.
 feynman       brute-force sum over colour-ordered Feynman diagrams with full
               vertex tensors -- an independent pin for ``bg``.
+states        the d-dimensional polarisation states of paper Sec. 2.3 and
+              their duals (square-root-free normalisation).
 closed_forms  Parke-Taylor (paper Sec. 3.1) and spinor brackets -- pins.
 
 Parity status per function is stated in each module header.
