@@ -165,6 +165,47 @@ def run_workload(kind: str, steps: int, warmup: int):
 
 
 # ----------------------------------------------------------------------------
+# polarisation states (d-dimensional states and duals of Sec. 2.3)
+# ----------------------------------------------------------------------------
+
+def run_states(steps: int, warmup: int, d: int = 6, npts: int = 1 << 20):
+    """States and duals of 2^20 massless d-vectors, F_p and complex128."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(12)
+    p = I.DEFAULT_PRIME
+    res = {}
+    for field in ("fp", "c128"):
+        if field == "fp":
+            k = I.fp_null(rng, p, (npts,), d).astype(np.uint32)
+            chi = I.fp_null(rng, p, (npts,), 4).astype(np.uint32)
+            tk = torch.from_numpy(np.ascontiguousarray(k.T).view(np.int32)).to(dev)
+            tc = torch.from_numpy(np.ascontiguousarray(chi.T).view(np.int32)).to(dev)
+            fn = lambda: bg.bg_states_fp(tk, tc, p)
+            s = 4
+        else:
+            k = I.random_null_c(rng, npts, d).astype(np.complex128)
+            chi = I.random_null_c(rng, npts, 4).astype(np.complex128)
+            tk = torch.from_numpy(np.ascontiguousarray(k.T)).to(dev)
+            tc = torch.from_numpy(np.ascontiguousarray(chi.T)).to(dev)
+            fn = lambda: bg.bg_states_c128(tk, tc)
+            s = 16
+        total_ms, launch_ms, _ = time_launches(fn, steps, warmup)
+        nbytes = npts * ((d + 4) * s + 2 * (d - 2) * d * s + 1)
+        achieved = nbytes / (launch_ms * 1e-3) / 1e9
+        res[field] = {"value": npts / (launch_ms * 1e-3), "unit": "points/s", "kernel_ms": launch_ms,
+                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS * 1e3,
+                                   "unit": "GB/s", "frac": achieved / (HBM_PEAK_TBS * 1e3), "traffic": None}}
+    return {"workload": f"d = {d} polarisation states and duals of 2^20 massless vectors (reference chi per "
+                        "point), F_p p = 2^31-19 and complex128", "d": d, "npts": npts, **res}
+
+
+# ----------------------------------------------------------------------------
 # batched form: 88 (field, n, d) groups in one call
 # ----------------------------------------------------------------------------
 
@@ -438,7 +479,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served"], default="both",
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states"],
+                    default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one device-to-device copy of MIB MiB: a plain copy "
@@ -456,6 +498,9 @@ def main(argv=None):
         return
     if a.workload == "served":
         print(json.dumps(run_served(a.serve_requests)), flush=True)
+        return
+    if a.workload == "states":
+        print(json.dumps(run_states(a.steps, a.warmup)), flush=True)
         return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
@@ -495,6 +540,7 @@ def main(argv=None):
             "variant": fp_run["variant"],
         },
     }
+    line["states"] = run_states(a.steps, a.warmup)
     if not a.no_batched:
         line["batched"] = run_batched(a.steps, a.warmup)
     if not a.no_served:

@@ -114,6 +114,41 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p,
                      uint32_t* out, uint8_t* status, void* hip_stream);
 
 /*
+ * Polarisation states of massless d-dimensional gluons (paper Sec. 2.3, in
+ * its square-root-free normalisation): for each point q, a massless d-vector
+ * k and a massless four-dimensional reference chi give the d - 2 states
+ * e_1..e_{d-2} and their duals e~_1..e~_{d-2} with k.e_i = 0,
+ * e_i.e~_j = -delta_ij and sum_i e_i^mu e~_i^nu = -g^{mu nu} + (k^mu eta^nu +
+ * eta^mu k^nu)/(k.eta), eta = (k^0..k^3, -k^4, ..., -k^{d-1}) (d >= 5):
+ *   k4 = (k^0..k^3, 0, ...), mu^2 = k4.k4, kb = k4 - mu^2/(2 chi.k4) chi,
+ *   e_1 = <kb|gamma|chi]/(2 [kb chi]),  e_2 = [kb|gamma|chi>/<kb chi>,
+ *   e~_1 = e_2, e~_2 = e_1,
+ *   e_3 = kb - mu^2/(2 chi.k4) chi, e~_3 = e_3/mu^2               (d >= 5),
+ *   e_4 = (0,0,0,0, k^5, -k^4, 0, ...), e~_4 = e_4/(k^4 k^4 + k^5 k^5) (d >= 6),
+ *   e_x^i = k^i k^{x+1} (4 <= i <= x), e_x^{x+1} = -mu_{x+1}^2,
+ *   e~_x = e_x/(mu_{x+1}^2 mu_{x+2}^2)  (5 <= x <= d-2), mu_y^2 = sum_{4<=i<y} (k^i)^2.
+ * Spinors of a massless four-vector v: lam = (1, (v^1 + i v^2)/v+),
+ * lamt = (v+, v^1 - i v^2) when v+ = v^0 + v^3 is non-zero (F_p) or
+ * |v+|^2 >= |v-|^2 (complex), else lam = ((v^1 - i v^2)/v-, 1),
+ * lamt = (v^1 + i v^2, v-), v- = v^0 - v^3.
+ *   d        4 <= d <= BG_MAX_D
+ *   momenta  device [d][ld] (k), chi device [4][ld]
+ *   eps, epst  device [d-2][d][ld]: state s, component mu at (s d + mu) ld + q
+ *   status   device uint8 [npts] or NULL: BG_PT_OK; BG_PT_SINGULAR when a
+ *            required denominator vanishes (chi.k4, a bracket, a spinor chart,
+ *            mu^2 products); BG_PT_BADRESIDUE (F_p) for an input >= p.  Both
+ *            outputs then hold the sentinel in every slot of the point.
+ * bg_states_fp needs p = 1 (mod 4) (BG_EDOMAIN otherwise): i is
+ * g^((p-1)/4) mod p for the smallest quadratic non-residue g.  Residues in
+ * and out are canonical.  Other arguments and errors as for bg_amplitudes_*.
+ */
+int bg_states_c128(int d, int64_t npts, int64_t ld, const double* momenta, const double* chi,
+                   double* eps, double* epst, uint8_t* status, void* hip_stream);
+int bg_states_fp(int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
+                 const uint32_t* chi, uint32_t* eps, uint32_t* epst, uint8_t* status,
+                 void* hip_stream);
+
+/*
  * Batched form: many (field, n, d) groups in one call.  Each group has the
  * layout and meaning of one bg_amplitudes_* call; every group is validated
  * before anything is enqueued (the first invalid group's error is returned).

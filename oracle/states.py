@@ -36,8 +36,8 @@ determinant v.v = 0 and equals lam lamt^T for
     lam = (1, vt / v+),   lamt = (v+, vtb)     if the "plus chart" is used,
     lam = (vtb / v-, 1),  lamt = (vt, v-)      otherwise;
 
-the plus chart is used when v+ != 0 (exact fields) or |v+| >= |v-|
-(complex binary64).  <ab> = a_1 b_2 - a_2 b_1 on lam, [ab] likewise on
+the plus chart is used when v+ != 0 (exact fields) or |v+|^2 >= |v-|^2
+(complex binary64, squares of real and imaginary parts summed).  <ab> = a_1 b_2 - a_2 b_1 on lam, [ab] likewise on
 lamt, and the four-vector of a rank-one matrix u w^T is
 ((M11 + M22)/2, (M12 + M21)/2, i (M12 - M21)/2, (M11 - M22)/2), so that
 <a|gamma|b] = 2 vec(lam_a lamt_b^T).
@@ -57,7 +57,7 @@ from .fields import mdot
 def _chart_plus(F, vp, vm):
     if F.name in ("fp", "q", "qi"):
         return not F.is_zero(vp)
-    return abs(vp) >= abs(vm)
+    return vp.real * vp.real + vp.imag * vp.imag >= vm.real * vm.real + vm.imag * vm.imag
 
 
 def spinors(F, v, i_unit):

@@ -34,6 +34,12 @@ _SIGNATURES = {
     "bg_amplitudes_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_states_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "bg_states_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
     "bg_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "bg_select_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "bg_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_int64,
@@ -209,6 +215,65 @@ def bg_amplitudes_fp(momenta, pols, p, out=None, status=None, npts=None, stream=
     if check and rc != BG_OK:
         raise BGError(rc, "bg_amplitudes_fp")
     return out, status
+
+
+# ----------------------------------------------------------------------------
+# polarisation states
+# ----------------------------------------------------------------------------
+
+def _check_rows(name, t, rows, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.shape[0] != rows or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous [{rows}][ld], got {tuple(t.shape)}")
+    return t.shape[1]
+
+
+def bg_states_c128(momenta, chi, npts=None, stream=None):
+    """States and duals of massless d-vectors over complex128.
+
+    momenta: [d][ld], chi: [4][ld] complex128 on the GPU.  Returns views
+    (eps [d-2][d][npts], epst [d-2][d][npts], status [npts]) of outputs laid
+    out with the inputs' leading dimension."""
+    import torch
+    d = momenta.shape[0]
+    ld = _check_rows("momenta", momenta, d, torch.complex128)
+    if _check_rows("chi", chi, 4, torch.complex128) != ld:
+        raise ValueError("momenta and chi must share ld")
+    npts = ld if npts is None else int(npts)
+    eps = torch.empty((max(d - 2, 0), d, ld), dtype=torch.complex128, device=momenta.device)
+    epst = torch.empty_like(eps)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=momenta.device)
+    rc = lib().bg_states_c128(d, npts, ld, _ptr(momenta), _ptr(chi), _ptr(eps), _ptr(epst), _ptr(st),
+                              _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_states_c128")
+    return eps[..., :npts], epst[..., :npts], st[:npts]
+
+
+def bg_states_fp(momenta, chi, p, npts=None, stream=None):
+    """States and duals of massless d-vectors over Z_p (p = 1 mod 4).
+
+    momenta: [d][ld], chi: [4][ld] 32-bit residues on the GPU.  Returns
+    views (eps [d-2][d][npts], epst [d-2][d][npts], status [npts])."""
+    import torch
+    d = momenta.shape[0]
+    dt = momenta.dtype
+    ld = _check_rows("momenta", momenta, d, dt)
+    if _check_rows("chi", chi, 4, dt) != ld:
+        raise ValueError("momenta and chi must share ld")
+    npts = ld if npts is None else int(npts)
+    eps = torch.empty((max(d - 2, 0), d, ld), dtype=dt, device=momenta.device)
+    epst = torch.empty_like(eps)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=momenta.device)
+    rc = lib().bg_states_fp(d, npts, ld, ctypes.c_uint32(p), _ptr(momenta), _ptr(chi), _ptr(eps), _ptr(epst),
+                            _ptr(st), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_states_fp")
+    return eps[..., :npts], epst[..., :npts], st[:npts]
 
 
 # ----------------------------------------------------------------------------

@@ -130,3 +130,18 @@ def test_server_argument_checks_without_gpu():
     assert L.bg_server_destroy(None) == bg.BG_OK
     t0 = bg.bg_server_now_ns()
     assert bg.bg_server_now_ns() >= t0
+
+
+def test_states_argument_checks():
+    """bg_states_*: dimension range, prime and p = 1 (mod 4), pointers."""
+    L = bg.lib()
+    D = ctypes.c_void_p(0x1000)
+    st = lambda d=6, npts=10, ld=10, p=2147483629, m=D, c=D, e=D, t=D: L.bg_states_fp(
+        d, npts, ld, ctypes.c_uint32(p), m, c, e, t, NULL, NULL)
+    assert st(d=3) == bg.BG_EDOMAIN and st(d=11) == bg.BG_EDOMAIN
+    assert st(p=2147483631) == bg.BG_ENOTPRIME
+    assert st(p=2147483647) == bg.BG_EDOMAIN        # prime, but 3 mod 4: no sqrt(-1)
+    assert st(m=NULL) == bg.BG_EINVAL and st(ld=5) == bg.BG_EINVAL
+    assert st(npts=0, ld=0, m=NULL, c=NULL, e=NULL, t=NULL) == bg.BG_OK
+    assert L.bg_states_c128(6, 10, 10, NULL, D, D, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_states_c128(2, 10, 10, D, D, D, D, NULL, NULL) == bg.BG_EDOMAIN
