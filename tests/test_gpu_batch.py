@@ -107,3 +107,56 @@ def test_invalid_group_rejects_whole_batch(torch_dev):
     torch.cuda.synchronize()
     assert (data[0]["st"] == 9).all()          # nothing ran
     bg.bg_batch_run([])                        # empty batch is fine
+
+
+def test_full_batched_workload_sampled(torch_dev):
+    """The measured batched workload itself (88 groups, 4*10^6 points, the
+    bench's launch configuration after autotuning): two sampled points per
+    group against the oracle, and no status other than OK."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import bench
+    torch, dev = torch_dev
+    groups = [g for g in I.batched_groups() if g["npts"] > 0]
+    with ProcessPoolExecutor(max_workers=bench._gen_workers(), mp_context=mp.get_context("spawn")) as ex:
+        soa = list(ex.map(bench._gen_group_soa, groups))
+    descs, keep = [], []
+    for g, (ks, es) in zip(groups, soa):
+        field = bg.BG_FIELD_FP if g["field"] == "fp" else bg.BG_FIELD_C128
+        bg.bg_autotune(field, g["n"], g["d"], P if g["field"] == "fp" else 0,
+                       npts=min(max(g["npts"], 4096), 1 << 18), reps=1)
+        if g["field"] == "fp":
+            tk = torch.from_numpy(ks.view(np.int32)).to(dev)
+            te = torch.from_numpy(es.view(np.int32)).to(dev)
+            out = torch.empty(g["npts"], dtype=torch.int32, device=dev)
+        else:
+            tk = torch.from_numpy(ks).to(dev)
+            te = torch.from_numpy(es).to(dev)
+            out = torch.empty(g["npts"], dtype=torch.complex128, device=dev)
+        st = torch.full((g["npts"],), 9, dtype=torch.uint8, device=dev)
+        descs.append(bg.make_group(tk, te, out, st, p=P))
+        keep.append((g, ks, es, out, st, tk, te))  # the descriptors hold raw pointers only
+    plan = bg.BatchPlan(descs)
+    try:
+        plan.launch()
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    rng = np.random.default_rng(3)
+    for g, ks, es, out, st, _, _ in keep:
+        sts = st.cpu().numpy()
+        assert (sts == 0).all(), (g["field"], g["n"], g["d"])
+        idx = rng.choice(g["npts"], size=min(2, g["npts"]), replace=False)
+        k = I.from_soa(ks[:, :, idx], len(idx))
+        e = I.from_soa(es[:, :, idx], len(idx))
+        o = out.cpu().numpy()[idx]
+        if g["field"] == "fp":
+            so, vo = bgtest.oracle_fp(k.astype(np.int64), e.astype(np.int64), P)
+            assert_fp_equal(sts[idx], o.view(np.uint32).astype(np.int64), so, vo, f"fp n={g['n']} d={g['d']}")
+        else:
+            so, vo = bgtest.oracle_c(k, e)
+            bgtest.check_c(o, vo, k, e, label=f"c128 n={g['n']} d={g['d']}")
+    for f in (bg.BG_FIELD_FP, bg.BG_FIELD_C128):
+        for g, *_ in keep:
+            bg.bg_select_variant(f, g["n"], g["d"], -1)
