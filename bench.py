@@ -159,7 +159,7 @@ def run_workload(kind: str, steps: int, warmup: int):
         "host_wall_ms_per_step": 1e3 * wall / steps,
         "npts": npts, "n": n, "d": d, "field": w["field"], "nonzero_status": bad,
         "work_per_amplitude": W, "roofline": roof,
-        "variant": next({k: v[k] for k in ("lanes", "comps_per_lane", "lds_tables", "generic")}
+        "variant": next({k: v[k] for k in ("lanes", "comps_per_lane", "lds_tables", "generic", "padded")}
                         for v, _ in tuned if v["index"] == chosen),
     }
 
@@ -300,7 +300,7 @@ def run_batched(steps: int, warmup: int):
         sel = next(v for v in bg.bg_variants(field, g["n"], g["d"]) if v["selected"])
         per_group.append({"field": g["field"], "n": g["n"], "d": g["d"], "npts": g["npts"], "ms": ms,
                           "roofline_ms": group_roofline_ms(g["field"], g["n"], g["d"], g["npts"]),
-                          "variant": {k: sel[k] for k in ("lanes", "comps_per_lane", "lds_tables", "generic")}})
+                          "variant": {k: sel[k] for k in ("lanes", "comps_per_lane", "lds_tables", "generic", "padded")}})
     per_group.sort(key=lambda r: -r["ms"])
     return {
         "workload": "88 groups (n 4..14 x d {4,6,8,10} x {complex128, Z_p}), 4*10^6 points, "

@@ -261,7 +261,10 @@ typedef struct {
   int lanes;            /* lanes cooperating on one point                      */
   int comps_per_lane;   /* Lorentz components held by each lane (>= d / lanes) */
   int lds_tables;       /* per-point scalar and momentum tables in LDS          */
-  int generic;          /* runtime-n kernel (tables in LDS, one point per lane) */
+  int generic;          /* runtime-n kernel (tables in LDS; lanes > 1: that many
+                           lanes share one point's tables)                       */
+  int padded;           /* lanes > 1 runtime-n kernel whose LDS table rows are
+                           padded to an odd number of 16-byte units            */
   int selected;         /* 1 if this variant is the one currently in use        */
 } bg_variant_info;
 

@@ -163,6 +163,8 @@ const Variant* default_variant(int field, int n, int d) {
     const bool fills = resident >= 512;
     if (!best || (fills && (best->L > v.L || !best_fills(best, N))) || (!fills && !best_fills(best, N) && v.L > best->L))
       best = &v;
+    else if (v.L == best->L && v.padded && !best->padded)
+      best = &v;  // padded rows are compiled only where they avoid bank conflicts
   }
   if (best) return best;
   for (const Variant& v : registry())
@@ -314,6 +316,7 @@ int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {
       o.comps_per_lane = reg[i].DL;
       o.lds_tables = reg[i].lds_tables ? 1 : 0;
       o.generic = reg[i].generic ? 1 : 0;
+      o.padded = reg[i].padded ? 1 : 0;
       o.selected = (&reg[i] == cur) ? 1 : 0;
     }
     ++count;

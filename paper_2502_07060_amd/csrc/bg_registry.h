@@ -26,6 +26,7 @@ struct Variant {
   int waves;        // minimum waves per SIMD the register allocation allows
   const void* fn;
   unsigned (*lds_per_point)(int N) = nullptr;  // runtime-n kernels: LDS bytes per point
+  bool padded = false;  // lane-group kernel whose table rows are padded to an odd number of 16-byte units
 };
 
 std::vector<Variant>& registry();
@@ -88,12 +89,12 @@ unsigned wide_lds_bytes(int N) {
       &generic_lds_bytes<GenericLayout<FLD<DMAX_, 1>, DMAX_>>});                                \
   }
 
-// runtime-n kernel with G lanes sharing each point's tables in LDS
-#define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_)                                              \
+// runtime-n kernel with G lanes sharing each point's tables (PAD: odd row stride)
+#define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_, PAD_)                                        \
   namespace bg {                                                                                \
-  template __global__ void bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_>(LaunchArgs, int);           \
+  template __global__ void bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_, PAD_>(LaunchArgs, int);     \
   static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
       FIELDTAG, 0, DMAX_, G_, 0, true, true, 1,                                                 \
-      reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_>),                 \
-      &wide_lds_bytes<WideLayout<FLD<DMAX_, 1>, DMAX_, G_>>});                                 \
+      reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_, PAD_>),           \
+      &wide_lds_bytes<WideLayout<FLD<DMAX_, 1>, DMAX_, G_, PAD_>>, PAD_});                     \
   }

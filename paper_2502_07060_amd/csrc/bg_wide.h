@@ -25,18 +25,34 @@
 // item order instead of split order, which changes only the rounding of the
 // complex path.  F_p propagator inverses: each lane inverts its share of the
 // denominators with one batched inversion and one Fermat power.
+//
+// LDS access.  A lane reads whole table rows, with 16-byte reads (complex
+// elements are 16 bytes; F_p rows when they start on 16-byte boundaries).
+// The lanes of a wave read rows of unrelated ranges at once, so a row stride
+// that is a multiple of 64 bytes (complex d = 4 or 8) sends most of them to
+// the same banks; the padded layouts round a row up to an odd number of
+// 16-byte units.  Complex sub-range momenta are direct left-to-right sums of
+// the legs (no prefix differences); a pair item reads each leg of S once for
+// both of its cuts.
 #pragma once
 
 #include "bg_generic.h"
 
 namespace bg {
 
-template <class Fld, int DMAX, int G>
+template <class Fld, int DMAX, int G, bool PAD>
 struct WideLayout {
   using E = typename Fld::E;
   using S = typename Fld::S;
   using A = typename Fld::A;
   static constexpr bool kFp = Fld::exact;
+  // row stride (elements) of the vector tables.  PAD makes a row an odd
+  // number of 16-byte units (complex: an odd element count; F_p: 4 or 12
+  // elements), so that rows start on every 16-byte bank group in turn and
+  // F_p rows can be read with 16-byte loads
+  static constexpr int kS = !PAD ? DMAX : (kFp ? 4 * (((DMAX + 3) / 4) | 1) : (DMAX | 1));
+  // F_p rows on 16-byte boundaries (the table bases are 16-byte aligned)
+  static constexpr bool kVec4 = kFp && kS % 4 == 0;
   struct Off {
     unsigned J, mom, epsn, nDh, nc, inv, part, pscal, flags, total;
   };
@@ -50,13 +66,13 @@ struct WideLayout {
   __host__ __device__ static Off offsets(int N) {
     Off o{};
     unsigned x = 0;
-    o.J = x;      x += up16((size_t)ncur(N) * DMAX * sizeof(E));
-    o.mom = x;    x += up16((size_t)(N + 1) * DMAX * sizeof(E));
+    o.J = x;      x += up16((size_t)ncur(N) * kS * sizeof(E));
+    o.mom = x;    x += up16((size_t)(N + 1) * kS * sizeof(E));
     o.epsn = x;   x += up16((size_t)DMAX * sizeof(E));
     o.nDh = x;    x += up16((size_t)ncur(N) * sizeof(S));
     o.nc = x;     x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
     o.inv = x;    x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
-    o.part = x;   x += up16((size_t)G * DMAX * sizeof(A));
+    o.part = x;   x += up16((size_t)G * kS * sizeof(A));
     o.pscal = x;  x += up16((size_t)G * sizeof(S));
     o.flags = x;  x += 16;
     o.total = x;
@@ -73,12 +89,13 @@ __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <class Fld, int DMAX, int G>
+template <class Fld, int DMAX, int G, bool PAD>
 struct WideRecursion {
   using E = typename Fld::E;
   using S = typename Fld::S;
   using A = typename Fld::A;
-  using Lay = WideLayout<Fld, DMAX, G>;
+  using Lay = WideLayout<Fld, DMAX, G, PAD>;
+  static constexpr int kS = Lay::kS;
   using Rec = Recursion<Fld, 2, DMAX, 1>;  // scalar helpers
   static constexpr bool kFp = Fld::exact;
   static constexpr bool kPairs = G < 32;
@@ -108,35 +125,106 @@ struct WideRecursion {
   }
 
   __device__ __forceinline__ int rid(int i, int j) const { return range_idx(N, i, j); }
-  __device__ __forceinline__ E& Jat(int r, int c) const { return Jt[r * DMAX + c]; }
-  __device__ __forceinline__ E& Mat(int l, int c) const { return Mt[l * DMAX + c]; }
-  __device__ __forceinline__ void loadJ(int r, E (&x)[DMAX]) const {
+  __device__ __forceinline__ E& Jat(int r, int c) const { return Jt[r * kS + c]; }
+  __device__ __forceinline__ E& Mat(int l, int c) const { return Mt[l * kS + c]; }
+  // one table row into registers with 16-byte LDS reads where the layout
+  // allows (complex elements are 16 bytes; F_p rows of a padded layout start
+  // on 16-byte boundaries)
+  __device__ __forceinline__ static void load_row(const E* row, E (&x)[DMAX]) {
+    if constexpr (!kFp) {
+      const double2* p = reinterpret_cast<const double2*>(row);
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) x[c] = Jt[r * DMAX + c];
-  }
-  __device__ __forceinline__ void loadM(int l, E (&x)[DMAX]) const {
+      for (int c = 0; c < DMAX; ++c) {
+        const double2 v = p[c];
+        x[c] = cplx{v.x, v.y};
+      }
+    } else if constexpr (Lay::kVec4) {
+      const int4* p4 = reinterpret_cast<const int4*>(row);
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) x[c] = Mt[l * DMAX + c];
+      for (int q = 0; q < DMAX / 4; ++q) {
+        const int4 v = p4[q];
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+      if constexpr (DMAX % 4 >= 2) {
+        const int2 v = reinterpret_cast<const int2*>(row)[DMAX / 4 * 2];
+        x[DMAX / 4 * 4] = v.x;
+        x[DMAX / 4 * 4 + 1] = v.y;
+      }
+      if constexpr (DMAX % 2 == 1) x[DMAX - 1] = row[DMAX - 1];
+    } else {
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) x[c] = row[c];
+    }
   }
+  __device__ __forceinline__ void loadJ(int r, E (&x)[DMAX]) const { load_row(Jt + r * kS, x); }
+  __device__ __forceinline__ void loadM(int l, E (&x)[DMAX]) const { load_row(Mt + l * kS, x); }
   // primed P_S (F_p: reduced, from prefix sums; complex: left-to-right sum of k')
   __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
     if constexpr (kFp) {
+      E a[DMAX], b[DMAX];
+      loadM(j + 1, a);
+      loadM(i, b);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(Mat(j + 1, c), Mat(i, c));
+      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(a[c], b[c]);
       P[0] = F.prime0(P[0]);
     } else {
       loadM(i, P);
       for (int l = i + 1; l <= j; ++l) {
+        E t[DMAX];
+        loadM(l, t);
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], Mat(l, c));
+        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], t[c]);
       }
     }
   }
   // F_p: primed P_S as unreduced differences Q_{j+1} - Q_i (|slot| <= 2h)
   __device__ __forceinline__ void lazyP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
+    E a[DMAX], b[DMAX];
+    loadM(j + 1, a);
+    loadM(i, b);
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) P[c] = Mat(j + 1, c) - Mat(i, c);
+    for (int c = 0; c < DMAX; ++c) P[c] = a[c] - b[c];
     P[0] = F.prime0(P[0]);
+  }
+  // complex: the primed momenta of both cuts c1 <= c2 of S = [i..j] in one
+  // pass over the legs, each leg read once and added to the two sums it
+  // belongs to, every sum still taken left to right:
+  //   legs i..c1 -> A1, A2;  c1+1..c2 -> B1, A2;  c2+1..j -> B1, B2
+  __device__ __forceinline__ void pair_momenta(int i, int j, int c1, int c2, E (&A1)[DMAX], E (&B1)[DMAX],
+                                               E (&A2)[DMAX], E (&B2)[DMAX]) const {
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) A1[c] = B1[c] = A2[c] = B2[c] = cplx{0.0, 0.0};
+    int l = i;
+    for (; l <= c1; ++l) {
+      E t[DMAX];
+      loadM(l, t);
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) {
+        A1[c] = cadd(A1[c], t[c]);
+        A2[c] = cadd(A2[c], t[c]);
+      }
+    }
+    for (; l <= c2; ++l) {
+      E t[DMAX];
+      loadM(l, t);
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) {
+        B1[c] = cadd(B1[c], t[c]);
+        A2[c] = cadd(A2[c], t[c]);
+      }
+    }
+    for (; l <= j; ++l) {
+      E t[DMAX];
+      loadM(l, t);
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) {
+        B1[c] = cadd(B1[c], t[c]);
+        B2[c] = cadd(B2[c], t[c]);
+      }
+    }
   }
 
   // ---- loads: eps into the table, momenta, eps_n; F_p prefix sums --------
@@ -220,10 +308,12 @@ struct WideRecursion {
   }
 
   // ---- one work item: contributions of cut c to K'(S), S = [i..j] ---------
-  // F_p: Pp holds unreduced differences, nDs accumulates -(J_A.J_B) / 2 as an
-  // int64 sum of products; complex: Pp is unused, nDs sums -(J_A.J_B).
+  // F_p: Pp holds P_S as unreduced differences, nDs accumulates -(J_A.J_B) / 2
+  // as an int64 sum of products; complex: PA, PB are the primed P_A, P_B
+  // (Pp unused), nDs sums -(J_A.J_B).
   template <class NDS>
-  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], A (&K)[DMAX], NDS& nDs) const {
+  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], const E (&PA)[DMAX],
+                      const E (&PB)[DMAX], A (&K)[DMAX], NDS& nDs) const {
     E JA[DMAX], JB[DMAX];
     const int ra = rid(i, c), rb = rid(c + 1, j);
     loadJ(ra, JA);
@@ -240,9 +330,7 @@ struct WideRecursion {
       F.fold(K);
       nDs = mad64(nDm, F.k.inv2, nDs);  // at most two terms per item
     } else {
-      E PA[DMAX], PB[DMAX], v[DMAX];
-      primedP(F, i, c, PA);
-      primedP(F, c + 1, j, PB);
+      E v[DMAX];
       const S n2 = F.ndot(PB, JA);
       const S n3 = F.ndot(PA, JB);
 #pragma unroll
@@ -306,19 +394,29 @@ struct WideRecursion {
           A Kp[DMAX];
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) Kp[c] = F.azero();
+          const int c1 = i + u, c2 = kPairs ? j - 1 - u : c1;
           if constexpr (kFp) {
             int64_t nDs = 0;
-            cut(F, i, j, i + u, Pp, Kp, nDs);
-            if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+            cut(F, i, j, c1, Pp, Pp, Pp, Kp, nDs);
+            if (kPairs && c2 != c1) cut(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
             pscal[g] = fp_redc2(fp_fold(nDs, F.k), F.k);  // -(sum of J_A.J_B) / 2
           } else {
             S nDs = F.szero();
-            cut(F, i, j, i + u, Pp, Kp, nDs);
-            if (kPairs && j - 1 - u != i + u) cut(F, i, j, j - 1 - u, Pp, Kp, nDs);
+            if constexpr (kPairs) {
+              E PA1[DMAX], PB1[DMAX], PA2[DMAX], PB2[DMAX];
+              pair_momenta(i, j, c1, c2, PA1, PB1, PA2, PB2);
+              cut(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
+              if (c2 != c1) cut(F, i, j, c2, Pp, PA2, PB2, Kp, nDs);
+            } else {
+              E PA[DMAX], PB[DMAX];
+              primedP(F, i, c1, PA);
+              primedP(F, c1 + 1, j, PB);
+              cut(F, i, j, c1, Pp, PA, PB, Kp, nDs);
+            }
             pscal[g] = nDs;
           }
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) part[g * DMAX + c] = Kp[c];
+          for (int c = 0; c < DMAX; ++c) part[g * kS + c] = Kp[c];
         }
         group_sync();
         if (own) {
@@ -327,7 +425,7 @@ struct WideRecursion {
           for (int kk = lo; kk < hi; ++kk) {
             const int slot = kk - k0;
 #pragma unroll
-            for (int c = 0; c < DMAX; ++c) K[c] = add_acc(F, K[c], part[slot * DMAX + c]);
+            for (int c = 0; c < DMAX; ++c) K[c] = add_acc(F, K[c], part[slot * kS + c]);
             nDsum = Rec::accumulate_scalar(F, nDsum, pscal[slot]);
           }
         }
@@ -343,7 +441,7 @@ struct WideRecursion {
           // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
           E QQ[DMAX];
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) QQ[c] = Mat(oi, c) + Mat(oj + 1, c);
+          for (int c = 0; c < DMAX; ++c) QQ[c] = Mat(oi, c) + Mat(oj + 1, c);  // once per range
           F.axpy(K, nDhS, QQ);
           F.fold(K);
         } else {
@@ -403,17 +501,17 @@ struct WideRecursion {
 
 // G lanes per point (G divides 64), blockDim.x / G points per block, LDS from the host
 // (points per block x WideLayout::offsets(N).total bytes).
-template <class Fld, int DMAX, int G>
+template <class Fld, int DMAX, int G, bool PAD>
 __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   extern __shared__ __align__(16) char lds[];
-  using Lay = WideLayout<Fld, DMAX, G>;
+  using Lay = WideLayout<Fld, DMAX, G, PAD>;
   static_assert(G >= 16 && 64 % G == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
   const int g = (int)(threadIdx.x % G);
   const int pb = (int)(threadIdx.x / G);
   const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / G) + pb;
   const bool valid = q0 < a.npts;
   const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
-  WideRecursion<Fld, DMAX, G> W(lds + (size_t)pb * Lay::offsets(N).total, N, g);
+  WideRecursion<Fld, DMAX, G, PAD> W(lds + (size_t)pb * Lay::offsets(N).total, N, g);
   typename Fld::S res;
   if constexpr (Fld::exact) {
     Fld F(a.fp, 0);
