@@ -13,7 +13,8 @@ Modules
 fields        exact F_p (Python ints), FP64 complex (Python complex) and Q
               (fractions.Fraction) arithmetic behind one small interface.
 bg            the recursion itself (paper Sec. 2.2, the current recursion and
-              the 3-/4-gluon vertices), memoised over contiguous sub-ranges.
+              the 3-/4-gluon vertices), memoised over contiguous sub-ranges;
+              mostly-minus or alternating metric (paper Sec. 3.1).
 feynman       brute-force sum over colour-ordered Feynman diagrams with full
               vertex tensors -- an independent pin for ``bg``.
 states        the d-dimensional polarisation states of paper Sec. 2.3 and

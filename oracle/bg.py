@@ -33,6 +33,11 @@ V4, and the sub-range momenta P_{i,j}):
   recursion reads (k_1..k_{n-1}, eps_1..eps_n) is not an integer in [0, p),
   status 2 and the sentinel are returned.  Status 2 takes precedence.
 
+* Metric: mostly-minus diag(1, -1, ..., -1) (paper Sec. 2.2) by default;
+  ``metric="alternating"`` uses diag(1, -1, 1, -1, ...) in every product
+  (the propagators' P_S^2, the vertices' contractions and the root), the
+  option paper Sec. 3.1 adds to match Caravel.
+
 Parity: pinned by tests/test_oracle_pins.py -- brute-force Feynman diagrams
 with full vertex tensors (``oracle.feynman``), Parke-Taylor for MHV and
 anti-MHV, the vanishing helicity configurations, the Ward identity, current
@@ -41,7 +46,7 @@ and cross-field agreement.
 """
 from __future__ import annotations
 
-from .fields import Fp, mdot
+from .fields import Fp, mdot, metric_dot
 
 STATUS_OK = 0
 STATUS_SINGULAR = 1
@@ -68,9 +73,10 @@ def subrange_momenta(F, k, N):
     return P
 
 
-def _kernel_vector(F, J, P, i, j, d):
+def _kernel_vector(F, J, P, i, j, d, mdot=mdot):
     """K(S) for S = [i..j]: the i-free bracket of the recursion, summed over
-    all V3 splits [i..s]|[s+1..j] and all V4 splits [i..s]|[s+1..t]|[t+1..j]."""
+    all V3 splits [i..s]|[s+1..j] and all V4 splits [i..s]|[s+1..t]|[t+1..j]
+    (``mdot`` is the metric's bilinear product)."""
     K = [F.zero] * d
     # three-gluon vertex, A = [i..s], B = [s+1..j]
     for s in range(i, j):
@@ -115,7 +121,7 @@ def _check_canonical(F, k, eps, n):
     return True
 
 
-def currents(F, k, eps):
+def currents(F, k, eps, metric="mostly-minus"):
     """All currents J(S), 1 <= |S| <= N-1, plus K([1..N]).
 
     Returns (status, J, Kroot) with J keyed by 0-based (i, j).  On a non-zero
@@ -126,6 +132,7 @@ def currents(F, k, eps):
         raise ValueError("need n >= 3 legs with one polarisation per leg")
     d = len(k[0])
     N = n - 1
+    dot = metric_dot(metric)
     if not _check_canonical(F, k, eps, n):
         return STATUS_BAD_RESIDUE, None, None
     P = subrange_momenta(F, k, N)
@@ -133,29 +140,29 @@ def currents(F, k, eps):
     for m in range(2, N):
         for i in range(0, N - m + 1):
             j = i + m - 1
-            K = _kernel_vector(F, J, P, i, j, d)
-            den = mdot(F, P[(i, j)], P[(i, j)])
+            K = _kernel_vector(F, J, P, i, j, d, dot)
+            den = dot(F, P[(i, j)], P[(i, j)])
             if F.is_zero(den):
                 return STATUS_SINGULAR, None, None
             inv = F.inv(den)
             J[(i, j)] = [F.mul(x, inv) for x in K]
-    Kroot = _kernel_vector(F, J, P, 0, N - 1, d)
+    Kroot = _kernel_vector(F, J, P, 0, N - 1, d, dot)
     return STATUS_OK, J, Kroot
 
 
-def amplitude(F, k, eps):
+def amplitude(F, k, eps, metric="mostly-minus"):
     """(status, M) for one phase-space point; M = eps_n . K([1..n-1])."""
-    status, _, Kroot = currents(F, k, eps)
+    status, _, Kroot = currents(F, k, eps, metric)
     if status != STATUS_OK:
         return status, sentinel(F)
-    return STATUS_OK, mdot(F, eps[-1], Kroot)
+    return STATUS_OK, metric_dot(metric)(F, eps[-1], Kroot)
 
 
-def amplitudes(F, k_pts, eps_pts):
+def amplitudes(F, k_pts, eps_pts, metric="mostly-minus"):
     """Loop of ``amplitude`` over points; returns (status list, value list)."""
     st, out = [], []
     for k, e in zip(k_pts, eps_pts):
-        s, m = amplitude(F, k, e)
+        s, m = amplitude(F, k, e, metric)
         st.append(s)
         out.append(m)
     return st, out

@@ -27,6 +27,9 @@ tensor).  Propagators are -i/P^2 (paper Sec. 2.2), the root amplitude is
 A = eps_n . T with the off-shell propagator removed.  With the recursion's
 M = eps_n . K([1..N]) (``oracle.bg``) the expected relation is A = i M.
 
+The metric is mostly-minus by default; ``metric="alternating"`` builds the
+tensors and the propagators from diag(1, -1, 1, -1, ...) instead.
+
 The caller passes the imaginary unit ``I`` of the field: ``1j`` over C, a
 square root of -1 mod p over F_p (exists for p = 1 mod 4).
 
@@ -35,7 +38,7 @@ checked in tests (the planar cubic+quartic tree counts).
 """
 from __future__ import annotations
 
-from .fields import mdot
+from .fields import metric_dot
 
 
 def trees(i, j):
@@ -56,11 +59,12 @@ def trees(i, j):
     return out
 
 
-def _metric(F, d):
+def _metric(F, d, metric="mostly-minus"):
+    """g^{mu nu} = g_{mu nu}: diag(1, -1, ..., -1), or diag(1, -1, 1, -1, ...)."""
     g = [[F.zero] * d for _ in range(d)]
-    g[0][0] = F.one
-    for mu in range(1, d):
-        g[mu][mu] = F.neg(F.one)
+    for mu in range(d):
+        plus = mu == 0 if metric == "mostly-minus" else mu % 2 == 0
+        g[mu][mu] = F.one if plus else F.neg(F.one)
     return g
 
 
@@ -119,13 +123,13 @@ def _v4_tensor(F, I, g, d):
     return V
 
 
-def _eval(F, I, g, V4, form, tree, k, eps, is_root):
+def _eval(F, I, g, V4, form, tree, k, eps, is_root, dot):
     """Returns (T or J vector with upper index, momentum flowing in)."""
     d = len(k[0])
     if tree[0] == "leaf":
         l = tree[1]
         return list(eps[l]), list(k[l])
-    kids = [_eval(F, I, g, V4, form, t, k, eps, False) for t in tree[1:]]
+    kids = [_eval(F, I, g, V4, form, t, k, eps, False, dot) for t in tree[1:]]
     Ps = [c[1] for c in kids]
     low = [_lower(F, g, c[0]) for c in kids]
     P = Ps[0]
@@ -144,20 +148,21 @@ def _eval(F, I, g, V4, form, tree, k, eps, is_root):
                               for nu in range(d) for rho in range(d) for sg in range(d)))
     if is_root:
         return T, P
-    prop = F.mul(F.neg(I), F.inv(mdot(F, P, P)))
+    prop = F.mul(F.neg(I), F.inv(dot(F, P, P)))
     return [F.mul(prop, x) for x in T], P
 
 
-def amplitude_diagrams(F, I, k, eps, form="paper"):
+def amplitude_diagrams(F, I, k, eps, form="paper", metric="mostly-minus"):
     """A = sum over diagrams of eps_n . T(root); returns (A, number of diagrams)."""
     n = len(k)
     N = n - 1
     d = len(k[0])
-    g = _metric(F, d)
+    dot = metric_dot(metric)
+    g = _metric(F, d, metric)
     V4 = _v4_tensor(F, I, g, d)
     total = F.zero
     diags = trees(0, N - 1)
     for tr in diags:
-        T, _ = _eval(F, I, g, V4, form, tr, k, eps, True)
-        total = F.add(total, mdot(F, eps[n - 1], T))
+        T, _ = _eval(F, I, g, V4, form, tr, k, eps, True, dot)
+        total = F.add(total, dot(F, eps[n - 1], T))
     return total, len(diags)

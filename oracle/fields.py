@@ -158,6 +158,28 @@ def mdot(F, x, y):
     return s
 
 
+def adot(F, x, y):
+    """Bilinear product in the alternating metric diag(1, -1, 1, -1, ...)
+    (the option of paper Sec. 3.1 that matches Caravel's convention):
+    x.y = sum_mu (-1)^mu x^mu y^mu."""
+    s = F.zero
+    for mu in range(len(x)):
+        t = F.mul(x[mu], y[mu])
+        s = F.add(s, t) if mu % 2 == 0 else F.sub(s, t)
+    return s
+
+
+METRICS = {"mostly-minus": mdot, "alternating": adot}
+
+
+def metric_dot(metric):
+    """The bilinear product of a metric name ("mostly-minus" or "alternating")."""
+    try:
+        return METRICS[metric]
+    except KeyError:
+        raise ValueError(f"unknown metric {metric!r}") from None
+
+
 def vadd(F, x, y):
     return [F.add(a, b) for a, b in zip(x, y)]
 
