@@ -164,6 +164,37 @@ def run_workload(kind: str, steps: int, warmup: int):
     }
 
 
+def run_alternating(kind: str, steps: int, warmup: int, mostly_minus_ms: float):
+    """The same workload through bg_amplitudes_*_metric in the alternating
+    metric of Sec. 3.1 (the loaders map it onto the mostly-minus one), against
+    the mostly-minus kernel time measured before."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    w = I.config_workload(kind)
+    dev = torch.device("cuda:0")
+    npts = len(w["k"])
+    alt = bg.BG_METRIC_ALTERNATING
+    if w["field"] == "fp":
+        tk = torch.from_numpy(I.to_soa(w["k"]).view(np.int32)).to(dev)
+        te = torch.from_numpy(I.to_soa(w["eps"]).view(np.int32)).to(dev)
+        out = torch.empty(npts, dtype=torch.int32, device=dev)
+        st = torch.empty(npts, dtype=torch.uint8, device=dev)
+        fn = lambda: bg.bg_amplitudes_fp(tk, te, w["p"], out=out, status=st, metric=alt)
+    else:
+        tk = torch.from_numpy(I.to_soa(w["k"])).to(dev)
+        te = torch.from_numpy(I.to_soa(w["eps"])).to(dev)
+        out = torch.empty(npts, dtype=torch.complex128, device=dev)
+        st = torch.empty(npts, dtype=torch.uint8, device=dev)
+        fn = lambda: bg.bg_amplitudes_c128(tk, te, out=out, status=st, metric=alt)
+    _, launch_ms, _ = time_launches(fn, steps, warmup)
+    return {"kernel_ms": launch_ms, "mostly_minus_kernel_ms": mostly_minus_ms,
+            "ratio": launch_ms / mostly_minus_ms, "value": npts / (launch_ms * 1e-3)}
+
+
 # ----------------------------------------------------------------------------
 # polarisation states (d-dimensional states and duals of Sec. 2.3)
 # ----------------------------------------------------------------------------
@@ -542,6 +573,11 @@ def main(argv=None):
             "roofline": fp_run["roofline"], "nonzero_status": fp_run["nonzero_status"],
             "variant": fp_run["variant"],
         },
+    }
+    line["alternating_metric"] = {
+        "workload": "the two n = 8 workloads through bg_amplitudes_*_metric, metric diag(1,-1,1,-1,...)",
+        "c8_d4": run_alternating("c8_d4", a.steps, a.warmup, main_run["kernel_ms"]),
+        "fp8_d6": run_alternating("fp8_d6", a.steps, a.warmup, fp_run["kernel_ms"]),
     }
     line["states"] = run_states(a.steps, a.warmup)
     if not a.no_batched:

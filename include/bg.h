@@ -114,6 +114,34 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p,
                      uint32_t* out, uint8_t* status, void* hip_stream);
 
 /*
+ * Metric of every Minkowski product (propagators P^2 and all contractions).
+ *   BG_METRIC_MOSTLY_MINUS  diag(1, -1, ..., -1)           (paper Sec. 2.2; the
+ *                           metric of bg_amplitudes_c128 / _fp and of every
+ *                           batched and served call)
+ *   BG_METRIC_ALTERNATING   diag(1, -1, 1, -1, 1, ...)     (paper Sec. 3.1, the
+ *                           convention of Caravel)
+ */
+enum { BG_METRIC_MOSTLY_MINUS = 0, BG_METRIC_ALTERNATING = 1 };
+
+/*
+ * bg_amplitudes_c128_metric, bg_amplitudes_fp_metric -- bg_amplitudes_c128
+ * and bg_amplitudes_fp with the metric chosen by `metric` (one of
+ * BG_METRIC_*; BG_EINVAL otherwise); the inputs are vectors in that metric
+ * (e.g. massless means k.k = 0 there).  Same layouts, outputs, statuses and
+ * errors.  The alternating metric is reached exactly by multiplying the
+ * components 2, 4, 6, ... of every input vector by a square root of -1 as it
+ * is loaded, which turns every product into the mostly-minus one; over Z_p
+ * this needs p = 1 (mod 4) (BG_EDOMAIN otherwise), with i = g^((p-1)/4) for
+ * the smallest quadratic non-residue g (M does not depend on the choice).
+ */
+int bg_amplitudes_c128_metric(int metric, int n, int d, int64_t npts, int64_t ld,
+                              const double* momenta, const double* pols,
+                              double* out, uint8_t* status, void* hip_stream);
+int bg_amplitudes_fp_metric(int metric, int n, int d, int64_t npts, int64_t ld, uint32_t p,
+                            const uint32_t* momenta, const uint32_t* pols,
+                            uint32_t* out, uint8_t* status, void* hip_stream);
+
+/*
  * Polarisation states of massless d-dimensional gluons (paper Sec. 2.3, in
  * its square-root-free normalisation): for each point q, a massless d-vector
  * k and a massless four-dimensional reference chi give the d - 2 states

@@ -23,6 +23,7 @@ BG_ENOMEM = -6
 BG_EBUSY = -7
 BG_PT_OK, BG_PT_SINGULAR, BG_PT_BADRESIDUE = 0, 1, 2
 BG_FIELD_C128, BG_FIELD_FP = 0, 1
+BG_METRIC_MOSTLY_MINUS, BG_METRIC_ALTERNATING = 0, 1
 BG_MAX_N, BG_MAX_D = 14, 10
 FP_SENTINEL = 0xFFFFFFFF
 
@@ -34,6 +35,12 @@ _SIGNATURES = {
     "bg_amplitudes_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_amplitudes_c128_metric": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_amplitudes_fp_metric": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                               ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bg_states_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -166,11 +173,13 @@ def _check_soa(name, t, n, d, dtype):
     return t.shape[2]
 
 
-def bg_amplitudes_c128(momenta, pols, out=None, status=None, npts=None, stream=None, check=True):
+def bg_amplitudes_c128(momenta, pols, out=None, status=None, npts=None, stream=None, check=True,
+                       metric=None):
     """M = eps_n . K([1..n-1]) per point over complex128.
 
     momenta, pols: complex128 tensors [n][d][ld] on the GPU.  Returns
-    (out complex128 [npts], status uint8 [npts]).
+    (out complex128 [npts], status uint8 [npts]).  ``metric`` (BG_METRIC_*)
+    selects bg_amplitudes_c128_metric; None is the mostly-minus call.
     """
     import torch
     n, d = momenta.shape[0], momenta.shape[1]
@@ -183,15 +192,25 @@ def bg_amplitudes_c128(momenta, pols, out=None, status=None, npts=None, stream=N
         out = torch.empty(npts, dtype=torch.complex128, device=dev)
     if status is None:
         status = torch.empty(npts, dtype=torch.uint8, device=dev)
-    rc = lib().bg_amplitudes_c128(n, d, npts, ld, _ptr(momenta), _ptr(pols), _ptr(out), _ptr(status),
-                                  _stream_ptr(stream))
+    if metric is None:
+        rc = lib().bg_amplitudes_c128(n, d, npts, ld, _ptr(momenta), _ptr(pols), _ptr(out), _ptr(status),
+                                      _stream_ptr(stream))
+    else:
+        rc = lib().bg_amplitudes_c128_metric(int(metric), n, d, npts, ld, _ptr(momenta), _ptr(pols), _ptr(out),
+                                             _ptr(status), _stream_ptr(stream))
     if check and rc != BG_OK:
-        raise BGError(rc, "bg_amplitudes_c128")
+        raise BGError(rc, "bg_amplitudes_c128" if metric is None else "bg_amplitudes_c128_metric")
     return out, status
 
 
-def bg_amplitudes_fp(momenta, pols, p, out=None, status=None, npts=None, stream=None, check=True):
-    """M mod p per point over Z_p.
+def bg_amplitudes_c128_metric(metric, momenta, pols, **kw):
+    """bg_amplitudes_c128 in the metric BG_METRIC_MOSTLY_MINUS or BG_METRIC_ALTERNATING."""
+    return bg_amplitudes_c128(momenta, pols, metric=metric, **kw)
+
+
+def bg_amplitudes_fp(momenta, pols, p, out=None, status=None, npts=None, stream=None, check=True,
+                     metric=None):
+    """M mod p per point over Z_p (``metric`` as for bg_amplitudes_c128).
 
     momenta, pols: tensors of uint32 residues [n][d][ld] (torch.uint32, or
     int32 holding the same bits).  Returns (out uint32-bits int32 [npts],
@@ -211,11 +230,20 @@ def bg_amplitudes_fp(momenta, pols, p, out=None, status=None, npts=None, stream=
         out = torch.empty(npts, dtype=dt, device=dev)
     if status is None:
         status = torch.empty(npts, dtype=torch.uint8, device=dev)
-    rc = lib().bg_amplitudes_fp(n, d, npts, ld, ctypes.c_uint32(p), _ptr(momenta), _ptr(pols), _ptr(out),
-                                _ptr(status), _stream_ptr(stream))
+    if metric is None:
+        rc = lib().bg_amplitudes_fp(n, d, npts, ld, ctypes.c_uint32(p), _ptr(momenta), _ptr(pols), _ptr(out),
+                                    _ptr(status), _stream_ptr(stream))
+    else:
+        rc = lib().bg_amplitudes_fp_metric(int(metric), n, d, npts, ld, ctypes.c_uint32(p), _ptr(momenta),
+                                           _ptr(pols), _ptr(out), _ptr(status), _stream_ptr(stream))
     if check and rc != BG_OK:
-        raise BGError(rc, "bg_amplitudes_fp")
+        raise BGError(rc, "bg_amplitudes_fp" if metric is None else "bg_amplitudes_fp_metric")
     return out, status
+
+
+def bg_amplitudes_fp_metric(metric, momenta, pols, p, **kw):
+    """bg_amplitudes_fp in the metric BG_METRIC_MOSTLY_MINUS or BG_METRIC_ALTERNATING."""
+    return bg_amplitudes_fp(momenta, pols, p, metric=metric, **kw)
 
 
 # ----------------------------------------------------------------------------

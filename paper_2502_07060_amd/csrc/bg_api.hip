@@ -83,6 +83,17 @@ FpConst make_fp_const(uint32_t p) {
   return k;
 }
 
+// a square root of -1 mod p (p = 1 mod 4) in Montgomery form: g^((p-1)/4) R
+// for the smallest quadratic non-residue g, balanced
+int32_t fp_sqrt_minus_one_mont(uint32_t p) {
+  uint64_t g = 2;
+  while (powmod(g, (p - 1) / 2, p) != p - 1) ++g;
+  const uint64_t i = powmod(g, (p - 1) / 4, p);
+  const uint64_t c32 = (uint64_t(1) << 32) % p;
+  const uint64_t R = (unsigned __int128)c32 * c32 % p;
+  return balanced((unsigned __int128)i * R % p, p);
+}
+
 // ---------------------------------------------------------------------------
 // variant choice
 // ---------------------------------------------------------------------------
@@ -198,6 +209,8 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.ld = ld;
   a.d = d;
   a.fp = fp;
+  a.metric = BG_METRIC_MOSTLY_MINUS;
+  a.ialt = 0;
   spec.fn = v->fn;
   spec.generic = v->generic;
   spec.lanes = v->L;
@@ -253,10 +266,13 @@ int enqueue(LaunchSpec& spec, hipStream_t stream) {
 }
 
 int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
-           void* out, uint8_t* status, const FpConst& fp, hipStream_t stream) {
+           void* out, uint8_t* status, const FpConst& fp, hipStream_t stream, int metric = BG_METRIC_MOSTLY_MINUS) {
   LaunchSpec spec;
   const int rc = prepare(field, n, d, npts, ld, momenta, pols, out, status, fp, spec);
-  return rc == BG_OK ? enqueue(spec, stream) : rc;
+  if (rc != BG_OK) return rc;
+  spec.args.metric = metric;
+  spec.args.ialt = (metric == BG_METRIC_ALTERNATING && field == FIELD_FP) ? fp_sqrt_minus_one_mont((uint32_t)fp.p) : 0;
+  return enqueue(spec, stream);
 }
 
 static int check_common(int n, int d, int64_t npts, int64_t ld) {
@@ -275,8 +291,9 @@ static int check_buffers(int64_t npts, int64_t ld, const void* m, const void* e,
 
 extern "C" {
 
-int bg_amplitudes_c128(int n, int d, int64_t npts, int64_t ld, const double* momenta,
-                       const double* pols, double* out, uint8_t* status, void* hip_stream) {
+int bg_amplitudes_c128_metric(int metric, int n, int d, int64_t npts, int64_t ld, const double* momenta,
+                              const double* pols, double* out, uint8_t* status, void* hip_stream) {
+  if (metric != BG_METRIC_MOSTLY_MINUS && metric != BG_METRIC_ALTERNATING) return BG_EINVAL;
   int rc = bg::check_common(n, d, npts, ld);
   if (rc != BG_OK) return rc;
   if (npts == 0) return BG_OK;
@@ -285,20 +302,35 @@ int bg_amplitudes_c128(int n, int d, int64_t npts, int64_t ld, const double* mom
   bg::FpConst none;
   memset(&none, 0, sizeof(none));
   return bg::launch(bg::FIELD_C128, n, d, npts, ld, momenta, pols, out, status, none,
-                    static_cast<hipStream_t>(hip_stream));
+                    static_cast<hipStream_t>(hip_stream), metric);
 }
 
-int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
-                     const uint32_t* pols, uint32_t* out, uint8_t* status, void* hip_stream) {
+int bg_amplitudes_c128(int n, int d, int64_t npts, int64_t ld, const double* momenta,
+                       const double* pols, double* out, uint8_t* status, void* hip_stream) {
+  return bg_amplitudes_c128_metric(BG_METRIC_MOSTLY_MINUS, n, d, npts, ld, momenta, pols, out, status,
+                                   hip_stream);
+}
+
+int bg_amplitudes_fp_metric(int metric, int n, int d, int64_t npts, int64_t ld, uint32_t p,
+                            const uint32_t* momenta, const uint32_t* pols, uint32_t* out, uint8_t* status,
+                            void* hip_stream) {
+  if (metric != BG_METRIC_MOSTLY_MINUS && metric != BG_METRIC_ALTERNATING) return BG_EINVAL;
   int rc = bg::check_common(n, d, npts, ld);
   if (rc != BG_OK) return rc;
   if (p < 3 || p >= 0x80000000u || !bg::is_prime_u32(p)) return BG_ENOTPRIME;
+  if (metric == BG_METRIC_ALTERNATING && p % 4 != 1) return BG_EDOMAIN;  // needs a square root of -1
   if (npts == 0) return BG_OK;
   rc = bg::check_buffers(npts, ld, momenta, pols, out);
   if (rc != BG_OK) return rc;
   const bg::FpConst k = bg::make_fp_const(p);
   return bg::launch(bg::FIELD_FP, n, d, npts, ld, momenta, pols, out, status, k,
-                    static_cast<hipStream_t>(hip_stream));
+                    static_cast<hipStream_t>(hip_stream), metric);
+}
+
+int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
+                     const uint32_t* pols, uint32_t* out, uint8_t* status, void* hip_stream) {
+  return bg_amplitudes_fp_metric(BG_METRIC_MOSTLY_MINUS, n, d, npts, ld, p, momenta, pols, out, status,
+                                 hip_stream);
 }
 
 int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {

@@ -51,6 +51,10 @@ struct LaunchArgs {
   int64_t ld;
   int d;
   FpConst fp;  // F_p only
+  // metric: 0 mostly-minus; 1 alternating diag(1, -1, 1, -1, ...), mapped onto
+  // the mostly-minus one on load (see Loader)
+  int metric;
+  int32_t ialt;  // F_p, alternating metric: a square root of -1 times R (Montgomery form)
 };
 
 // ---------------------------------------------------------------------------
@@ -60,11 +64,22 @@ struct LaunchArgs {
 // afterwards), so the compiler can issue all of a point's loads back to back
 // and wait once.  On F_p the largest raw residue seen is kept in `maxraw`;
 // the point has a bad residue iff it ends up >= p.
+//
+// Alternating metric (paper Sec. 3.1, diag(1, -1, 1, -1, ...)).  Multiplying
+// the components 2, 4, 6, ... of every vector by a square root i of -1 maps
+// x.y in that metric onto the mostly-minus product of the images
+// ((i x^mu)(i y^mu) (-1) = +x^mu y^mu), and the amplitude is built from such
+// products alone, so the loaders apply the map and every kernel runs
+// unchanged.  Exact in both fields: over C it swaps and negates parts, over
+// F_p it is one Montgomery product with i R.  ALT is a compile-time switch so
+// that the mostly-minus loads carry no trace of it (the register kernel
+// branches once, at its entry, between two instantiations of its body).
 template <class Fld>
 struct Loader;
 
 template <int DL, int L>
 struct Loader<FpField<DL, L>> {
+  template <bool ALT = false>
   __device__ static int32_t get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                                 uint32_t& maxraw) {
     const bool in = mu < a.d;
@@ -73,18 +88,36 @@ struct Loader<FpField<DL, L>> {
     const uint32_t xi = in ? x : 0u;
     maxraw = maxraw > xi ? maxraw : xi;
     const uint32_t xc = xi < (uint32_t)a.fp.p ? xi : 0u;
-    return fp_from_canonical(xc, a.fp);
+    int32_t v = fp_from_canonical(xc, a.fp);
+    if constexpr (ALT) {
+      if (mu >= 2 && (mu & 1) == 0) v = fp_mul(v, a.ialt, a.fp);
+    }
+    return v;
+  }
+  // the metric chosen at run time (lane-group and one-point-per-lane kernels)
+  __device__ static int32_t get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
+                                   uint32_t& maxraw) {
+    return a.metric != 0 ? get<true>(a, base, l, mu, q, maxraw) : get<false>(a, base, l, mu, q, maxraw);
   }
 };
 
 template <int DL, int L>
 struct Loader<C128Field<DL, L>> {
+  template <bool ALT = false>
   __device__ static cplx get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                              uint32_t&) {
     const bool in = mu < a.d;
     const double2 v =
         static_cast<const double2*>(base)[((int64_t)l * a.d + (in ? mu : 0)) * a.ld + q];
-    return in ? cplx{v.x, v.y} : cplx{0.0, 0.0};
+    if (!in) return cplx{0.0, 0.0};
+    if constexpr (ALT) {
+      if (mu >= 2 && (mu & 1) == 0) return cplx{-v.y, v.x};  // times i, exactly
+    }
+    return cplx{v.x, v.y};
+  }
+  __device__ static cplx get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
+                                uint32_t& maxraw) {
+    return a.metric != 0 ? get<true>(a, base, l, mu, q, maxraw) : get<false>(a, base, l, mu, q, maxraw);
   }
 };
 
@@ -182,7 +215,7 @@ struct Recursion {
     }
   }
 
-  template <int BLOCK>
+  template <int BLOCK, bool ALT>
   __device__ static void run(const Fld& F, const LaunchArgs& a, int64_t q, int s, uint32_t& bad,
                              bool& singular, S& result, Lds<BLOCK>* lds) {
     constexpr bool kFp = Fld::exact;
@@ -220,8 +253,8 @@ struct Recursion {
       E k[DL];
 #pragma unroll
       for (int c = 0; c < DL; ++c) {
-        k[c] = Loader<Fld>::get(a, a.momenta, l, mu0 + c, q, bad);
-        J[R::idx(l, l)][c] = Loader<Fld>::get(a, a.pols, l, mu0 + c, q, bad);
+        k[c] = Loader<Fld>::template get<ALT>(a, a.momenta, l, mu0 + c, q, bad);
+        J[R::idx(l, l)][c] = Loader<Fld>::template get<ALT>(a, a.pols, l, mu0 + c, q, bad);
       }
       k[0] = F.prime0(k[0]);
       if constexpr (kFp) {
@@ -235,7 +268,7 @@ struct Recursion {
       }
     });
 #pragma unroll
-    for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::get(a, a.pols, N, mu0 + c, q, bad);
+    for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::template get<ALT>(a, a.pols, N, mu0 + c, q, bad);
 
     // ---- a3/a4 (F_p): all propagator denominators, one batched inversion -----
     if constexpr (kFp) {
@@ -483,7 +516,8 @@ void bg_recursion_kernel(LaunchArgs a) {
   typename Fld::S res;
   if constexpr (Fld::exact) {
     Fld F(a.fp, s);
-    Rec::run(F, a, q, s, bad, singular, res, &lds);
+    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, &lds);
+    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, &lds);
     if constexpr (L > 1)
       bad = group_sum<L>(bad, [](uint32_t x, uint32_t y) { return x > y ? x : y; },
                          [](auto ctrl, uint32_t v) { return dpp_u32<decltype(ctrl)::value>(v); });
@@ -504,7 +538,8 @@ void bg_recursion_kernel(LaunchArgs a) {
     }
   } else {
     Fld F(s);
-    Rec::run(F, a, q, s, bad, singular, res, &lds);
+    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, &lds);
+    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, &lds);
     if (valid && s == 0) {
       double2 o;
       if (singular) {

@@ -44,6 +44,8 @@ struct LaunchSpec {
 };
 
 FpConst make_fp_const(uint32_t p);
+// a square root of -1 mod p (p = 1 mod 4) times R = 2^64, balanced
+int32_t fp_sqrt_minus_one_mont(uint32_t p);
 bool is_prime_u32(uint32_t n);
 int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
             void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec);

@@ -393,11 +393,8 @@ int launch_states(bool fp, int d, int64_t npts, int64_t ld, uint32_t p, const vo
   a.d = d;
   if (fp) {
     a.fp = make_fp_const(p);
-    int64_t g = 2;
-    while (powmod64(g, (p - 1) / 2, p) != (int64_t)p - 1) ++g;
-    const int64_t ip = powmod64(g, (p - 1) / 4, p);
     const int64_t R = powmod64(2, 64, p);
-    a.i_rep = balanced32(mulmod(ip, R, p), p);
+    a.i_rep = fp_sqrt_minus_one_mont(p);
     a.r2 = balanced32(mulmod(R, R, p), p);
   }
   const int64_t blocks = (npts + 255) / 256;

@@ -48,37 +48,40 @@ def _close_pool():
         _POOL = None
 
 
+MM = "mostly-minus"
+
+
 def _fp_one(args):
-    p, k, e = args
+    p, k, e, metric = args
     F = fields.Fp(p)
-    return obg.amplitude(F, [[int(x) for x in v] for v in k], [[int(x) for x in v] for v in e])
+    return obg.amplitude(F, [[int(x) for x in v] for v in k], [[int(x) for x in v] for v in e], metric)
 
 
 def _c_one(args):
-    k, e = args
+    k, e, metric = args
     F = fields.Complex128()
-    return obg.amplitude(F, [[complex(x) for x in v] for v in k], [[complex(x) for x in v] for v in e])
+    return obg.amplitude(F, [[complex(x) for x in v] for v in k], [[complex(x) for x in v] for v in e], metric)
 
 
 def _exact_one(args):
-    k, e = args
+    k, e, metric = args
     G = fields.GaussianRationals()
     st, m = obg.amplitude(G, [[G.elem(complex(x)) for x in v] for v in k],
-                          [[G.elem(complex(x)) for x in v] for v in e])
+                          [[G.elem(complex(x)) for x in v] for v in e], metric)
     return st, (G.to_complex(m) if st == 0 else complex("nan"))
 
 
-def oracle_fp(k, e, p):
+def oracle_fp(k, e, p, metric=MM):
     """k, e: (npts, n, d) integer arrays -> (status array, value array int64)."""
-    jobs = [(p, k[i], e[i]) for i in range(len(k))]
+    jobs = [(p, k[i], e[i], metric) for i in range(len(k))]
     res = pool().map(_fp_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
     st = np.array([r[0] for r in res], np.uint8)
     val = np.array([r[1] for r in res], np.int64)
     return st, val
 
 
-def oracle_c(k, e):
-    jobs = [(k[i], e[i]) for i in range(len(k))]
+def oracle_c(k, e, metric=MM):
+    jobs = [(k[i], e[i], metric) for i in range(len(k))]
     res = pool().map(_c_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
     st = np.array([r[0] for r in res], np.uint8)
     val = np.array([r[1] for r in res], np.complex128)
@@ -86,21 +89,21 @@ def oracle_c(k, e):
 
 
 def _err_one(args):
-    k, e = args
+    k, e, metric = args
     R = fields.RunningError()
-    st, m = obg.amplitude(R, [[R.elem(x) for x in v] for v in k], [[R.elem(x) for x in v] for v in e])
+    st, m = obg.amplitude(R, [[R.elem(x) for x in v] for v in k], [[R.elem(x) for x in v] for v in e], metric)
     return m[1] if st == 0 else float("inf")
 
 
-def error_bound_c(k, e):
+def error_bound_c(k, e, metric=MM):
     """u * e(M): the oracle's running rounding-error bound per point."""
-    jobs = [(k[i], e[i]) for i in range(len(k))]
+    jobs = [(k[i], e[i], metric) for i in range(len(k))]
     res = pool().map(_err_one, jobs, chunksize=max(1, len(jobs) // (4 * _workers())))
     return np.array(res) * 2.0 ** -53
 
 
-def exact_c(k, e):
-    jobs = [(k[i], e[i]) for i in range(len(k))]
+def exact_c(k, e, metric=MM):
+    jobs = [(k[i], e[i], metric) for i in range(len(k))]
     res = pool().map(_exact_one, jobs, chunksize=1)
     return np.array([r[1] for r in res], np.complex128)
 
@@ -111,21 +114,21 @@ def natural_size(k, e):
     return np.prod(np.linalg.norm(e, axis=-1), axis=1) * scale ** (4 - n)
 
 
-def check_c(gpu, ref, k, e, rel=1e-11, label=""):
+def check_c(gpu, ref, k, e, rel=1e-11, label="", metric=MM):
     """Apply the tolerance rule; returns the number of points that needed the
     rounding-error floor and the number that needed exact arbitration."""
     err = np.abs(gpu - ref)
     bad = np.nonzero(~(err <= rel * np.abs(ref)))[0]
     if bad.size == 0:
         return 0, 0
-    ub = error_bound_c(k[bad], e[bad])
+    ub = error_bound_c(k[bad], e[bad], metric)
     still = bad[~(err[bad] <= rel * np.abs(ref[bad]) + 2 * ub)]
     if still.size == 0:
         return bad.size, 0
     assert still.size <= max(3, len(gpu) // 1000), (
         f"{label}: {still.size} of {len(gpu)} points outside tolerance, first {still[:5]}, "
         f"err {err[still[:5]]}, |ref| {np.abs(ref[still[:5]])}")
-    ex = exact_c(k[still], e[still])
+    ex = exact_c(k[still], e[still], metric)
     for t, idx in enumerate(still):
         e_gpu = abs(gpu[idx] - ex[t])
         e_orc = abs(ref[idx] - ex[t])

@@ -145,3 +145,22 @@ def test_states_argument_checks():
     assert st(npts=0, ld=0, m=NULL, c=NULL, e=NULL, t=NULL) == bg.BG_OK
     assert L.bg_states_c128(6, 10, 10, NULL, D, D, D, NULL, NULL) == bg.BG_EINVAL
     assert L.bg_states_c128(2, 10, 10, D, D, D, D, NULL, NULL) == bg.BG_EDOMAIN
+
+
+def test_metric_argument_checks():
+    """bg_amplitudes_*_metric: metric tag, p = 1 (mod 4) for the alternating
+    metric over Z_p, and the checks of the plain entry points."""
+    L = bg.lib()
+    D = ctypes.c_void_p(0x1000)
+    fp = lambda metric=1, n=5, d=6, npts=10, ld=10, p=2147483629, m=D: L.bg_amplitudes_fp_metric(
+        metric, n, d, npts, ld, ctypes.c_uint32(p), m, D, D, NULL, NULL)
+    assert fp(metric=2) == bg.BG_EINVAL and fp(metric=-1) == bg.BG_EINVAL
+    assert fp(p=2147483647) == bg.BG_EDOMAIN            # prime, but 3 mod 4: no sqrt(-1)
+    assert fp(p=2147483631) == bg.BG_ENOTPRIME
+    assert fp(n=15) == bg.BG_EDOMAIN and fp(m=NULL) == bg.BG_EINVAL
+    assert fp(npts=0, ld=0, m=NULL) == bg.BG_OK
+    assert fp(metric=0, p=2147483647, npts=0, ld=0) == bg.BG_OK   # mostly-minus: any odd prime
+    c = lambda metric=1, n=5, d=6, npts=10, ld=10, m=D: L.bg_amplitudes_c128_metric(
+        metric, n, d, npts, ld, m, D, D, NULL, NULL)
+    assert c(metric=7) == bg.BG_EINVAL and c(d=0) == bg.BG_EDOMAIN and c(ld=3) == bg.BG_EINVAL
+    assert c(npts=0, ld=0, m=NULL) == bg.BG_OK

@@ -27,7 +27,7 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def gpu_fp(torch_dev, k, e, p, ld=None, pad_value=None):
+def gpu_fp(torch_dev, k, e, p, ld=None, pad_value=None, metric=None):
     torch, dev = torch_dev
     npts = len(k)
     ks, es = I.to_soa(k.astype(np.uint32), ld), I.to_soa(e.astype(np.uint32), ld)
@@ -36,16 +36,16 @@ def gpu_fp(torch_dev, k, e, p, ld=None, pad_value=None):
         es[:, :, npts:] = pad_value
     tk = torch.from_numpy(ks.view(np.int32)).to(dev)
     te = torch.from_numpy(es.view(np.int32)).to(dev)
-    out, st = bg.bg_amplitudes_fp(tk, te, p, npts=npts)
+    out, st = bg.bg_amplitudes_fp(tk, te, p, npts=npts, metric=metric)
     torch.cuda.synchronize()
     return st.cpu().numpy(), out.cpu().numpy().view(np.uint32).astype(np.int64)
 
 
-def gpu_c(torch_dev, k, e, ld=None):
+def gpu_c(torch_dev, k, e, ld=None, metric=None):
     torch, dev = torch_dev
     tk = torch.from_numpy(I.to_soa(k.astype(np.complex128), ld)).to(dev)
     te = torch.from_numpy(I.to_soa(e.astype(np.complex128), ld)).to(dev)
-    out, st = bg.bg_amplitudes_c128(tk, te, npts=len(k))
+    out, st = bg.bg_amplitudes_c128(tk, te, npts=len(k), metric=metric)
     torch.cuda.synchronize()
     return st.cpu().numpy(), out.cpu().numpy()
 

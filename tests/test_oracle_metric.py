@@ -47,8 +47,10 @@ def null_alt(rng, d, p=P):
 
 
 def physical_alt(rng, n, d, p=P):
-    """n massless momenta (alternating metric) summing to zero, and transverse
-    polarisations eps_l = v_l - (v_l.k_l)/(q.k_l) q."""
+    """n >= 4 massless momenta (alternating metric) summing to zero, and
+    transverse polarisations eps_l = v_l - (v_l.k_l)/(q.k_l) q."""
+    if n < 4:
+        raise ValueError("three massless momenta summing to zero have no transverse states here")
     F = fields.Fp(p)
     dot = fields.adot
     while True:
