@@ -19,7 +19,8 @@ feynman       brute-force sum over colour-ordered Feynman diagrams with full
               vertex tensors -- an independent pin for ``bg``.
 states        the d-dimensional polarisation states of paper Sec. 2.3 and
               their duals (square-root-free normalisation).
-closed_forms  Parke-Taylor (paper Sec. 3.1) and spinor brackets -- pins.
+rational      residues of rationals, Chinese remaindering and rational
+              reconstruction (F_p samples back to Q).
 
 Parity status per function is stated in each module header.
 """
