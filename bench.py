@@ -196,6 +196,79 @@ def run_alternating(kind: str, steps: int, warmup: int, mostly_minus_ms: float):
 
 
 # ----------------------------------------------------------------------------
+# rational amplitudes from F_p samples (residues, F_p amplitudes, reconstruction)
+# ----------------------------------------------------------------------------
+
+def _largest_primes_below(top: int, count: int):
+    out, c = [], top - 1
+    while len(out) < count:
+        if c % 2 and all(c % f for f in range(3, int(c ** 0.5) + 1, 2)):
+            out.append(c)
+        c -= 1
+    return out
+
+
+def run_rational(steps: int, warmup: int, n: int = 5, d: int = 4, npts: int = 1 << 18, nprimes: int = 14,
+                 pool: int = 512):
+    """Rational amplitudes at rational kinematic points: for each prime the
+    inputs' residues (bg_fp_from_rational) and the F_p amplitudes
+    (bg_amplitudes_fp), then Chinese remaindering and rational reconstruction
+    (bg_rational_reconstruct), all on the GPU with inputs resident."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    primes = _largest_primes_below(2 ** 31, nprimes)
+    kn, kd, en, ed = I.rational_points(11, n, d, pool)
+    reps = npts // pool
+    soa = lambda a: torch.from_numpy(np.ascontiguousarray(np.tile(np.transpose(a, (1, 2, 0)), (1, 1, reps)))).to(dev)
+    tkn, tkd, ten, ted = soa(kn), soa(kd), soa(en), soa(ed)
+    km = torch.empty((n, d, npts), dtype=torch.int32, device=dev)
+    em = torch.empty_like(km)
+    kst = torch.empty((n, d, npts), dtype=torch.uint8, device=dev)
+    est = torch.empty_like(kst)
+    res = torch.empty((nprimes, npts), dtype=torch.int32, device=dev)
+    ast = torch.empty((nprimes, npts), dtype=torch.uint8, device=dev)
+    bg.bg_autotune(bg.BG_FIELD_FP, n, d, primes[0], npts=npts, reps=3)
+
+    def residues_and_amplitudes():
+        for i, p in enumerate(primes):
+            bg.bg_fp_from_rational(p, tkn, tkd, out=km, status=kst)
+            bg.bg_fp_from_rational(p, ten, ted, out=em, status=est)
+            bg.bg_amplitudes_fp(km, em, p, out=res[i], status=ast[i])
+
+    box = {}
+
+    def reconstruct():
+        box["r"] = bg.bg_rational_reconstruct(primes, res)
+
+    def whole():
+        residues_and_amplitudes()
+        reconstruct()
+
+    total_ms, launch_ms, _ = time_launches(whole, steps, warmup)
+    _, rr_ms, _ = time_launches(reconstruct, steps, warmup)
+    _, fa_ms, _ = time_launches(residues_and_amplitudes, steps, warmup)
+    num, den, st = box["r"]
+    bad = int((st != 0).sum().item()) + int((ast != 0).sum().item())
+    L = bg.bg_rr_limbs(nprimes)
+    rr_bytes = npts * (4 * nprimes + 8 * L + 1)
+    return {
+        "workload": f"n={n}, d={d} rational kinematic points (light-cone integers in [-9, 9], exact closing pair, "
+                    f"integer w in [-5, 5]; {pool} distinct points tiled to {npts}), {nprimes} primes below 2^31",
+        "value": npts / (total_ms * 1e-3), "unit": "rational amplitudes/s",
+        "ms_per_step": total_ms / steps, "ms_residues_and_fp_amplitudes": fa_ms, "ms_reconstruct": rr_ms,
+        "reconstruct": {"bound": "hbm", "achieved": rr_bytes / (rr_ms * 1e-3) / 1e9, "peak": HBM_PEAK_TBS * 1e3,
+                        "unit": "GB/s", "frac": rr_bytes / (rr_ms * 1e-3) / (HBM_PEAK_TBS * 1e12),
+                        "points_per_s": npts / (rr_ms * 1e-3)},
+        "nonzero_status": bad, "npts": npts, "nprimes": nprimes,
+    }
+
+
+# ----------------------------------------------------------------------------
 # polarisation states (d-dimensional states and duals of Sec. 2.3)
 # ----------------------------------------------------------------------------
 
@@ -513,7 +586,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states"],
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational"],
                     default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -535,6 +608,9 @@ def main(argv=None):
         return
     if a.workload == "states":
         print(json.dumps(run_states(a.steps, a.warmup)), flush=True)
+        return
+    if a.workload == "rational":
+        print(json.dumps(run_rational(a.steps, a.warmup)), flush=True)
         return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
@@ -580,6 +656,7 @@ def main(argv=None):
         "fp8_d6": run_alternating("fp8_d6", a.steps, a.warmup, fp_run["kernel_ms"]),
     }
     line["states"] = run_states(a.steps, a.warmup)
+    line["rational"] = run_rational(a.steps, a.warmup)
     if not a.no_batched:
         line["batched"] = run_batched(a.steps, a.warmup)
     if not a.no_served:

@@ -177,6 +177,52 @@ int bg_states_fp(int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* mo
                  void* hip_stream);
 
 /*
+ * From Z_p samples back to rational numbers (paper Sec. 1 and Sec. 3: values
+ * computed over F_p at rational kinematic points are reconstructed as
+ * rationals, e.g. to compare with another program's result).
+ *
+ * bg_fp_from_rational -- residues of fractions, elementwise:
+ *   out[i] = num[i] / den[i] mod p, canonical in [0, p)
+ *   p        odd prime below 2^31 (BG_ENOTPRIME otherwise)
+ *   count    number of values (>= 0)
+ *   num, den device int64 [count]; out device uint32 [count]
+ *   status   device uint8 [count] or NULL: 0, or 1 when p divides den[i]
+ *            (out[i] = 0xFFFFFFFF)
+ * Use it to map rational momenta and polarisations onto each prime before
+ * bg_amplitudes_fp.
+ *
+ * bg_rational_reconstruct -- Chinese remaindering and rational
+ * reconstruction, one point per lane.  With M = p_1 ... p_k and
+ * B = floor(sqrt((M - 1) / 2)), the residues r_i give the unique
+ * 0 <= x < M with x = r_i (mod p_i); the extended Euclidean algorithm on
+ * (M, x) is run to the first remainder r <= B, with cofactor t; the result is
+ * a / b = sign(t) r / |t| when 0 < |t| <= B and gcd(t, M) = 1 (Wang's
+ * rational reconstruction, as in von zur Gathen and Gerhard, Modern Computer
+ * Algebra, Sec. 5.10).  Any fraction with |a| <= B, 0 < b <= B,
+ * gcd(a, b) = 1 and a = b x (mod M) is unique, and is the one returned.
+ *   nprimes  1 <= nprimes <= BG_RR_MAX_PRIMES (BG_EINVAL otherwise)
+ *   primes   host uint32 [nprimes]: distinct odd primes below 2^31
+ *            (BG_ENOTPRIME / BG_EINVAL)
+ *   residues device uint32 [nprimes][ld]: the value modulo primes[i] of
+ *            point q at i * ld + q (e.g. the out arrays of bg_amplitudes_fp)
+ *   num      device int32 [L][ld], L = BG_RR_LIMBS(nprimes): a in two's
+ *            complement, 32-bit limbs least significant first
+ *   den      device uint32 [L][ld]: b, same limb order
+ *   status   device uint8 [npts] or NULL: 0 reconstructed; 1 no fraction
+ *            within the bound (more primes are needed); 2 a residue is not
+ *            in [0, p_i) (e.g. the sentinel of a singular point).  num and
+ *            den are zero unless the status is 0.
+ * Both calls are asynchronous on hip_stream and allocate nothing.
+ */
+#define BG_RR_MAX_PRIMES 32
+#define BG_RR_LIMBS(nprimes) (((nprimes) + 2) / 2)
+int bg_fp_from_rational(uint32_t p, int64_t count, const int64_t* num, const int64_t* den,
+                        uint32_t* out, uint8_t* status, void* hip_stream);
+int bg_rational_reconstruct(int nprimes, const uint32_t* primes, int64_t npts, int64_t ld,
+                            const uint32_t* residues, int32_t* num, uint32_t* den,
+                            uint8_t* status, void* hip_stream);
+
+/*
  * Batched form: many (field, n, d) groups in one call.  Each group has the
  * layout and meaning of one bg_amplitudes_* call; every group is validated
  * before anything is enqueued (the first invalid group's error is returned).

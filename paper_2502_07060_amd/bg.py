@@ -41,6 +41,11 @@ _SIGNATURES = {
     "bg_amplitudes_fp_metric": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_fp_from_rational": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_rational_reconstruct": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "bg_states_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -303,6 +308,78 @@ def bg_states_fp(momenta, chi, p, npts=None, stream=None):
     if rc != BG_OK:
         raise BGError(rc, "bg_states_fp")
     return eps[..., :npts], epst[..., :npts], st[:npts]
+
+
+# ----------------------------------------------------------------------------
+# from Z_p samples back to rationals
+# ----------------------------------------------------------------------------
+
+BG_RR_MAX_PRIMES = 32
+
+
+def bg_rr_limbs(nprimes: int) -> int:
+    """Limbs per value of bg_rational_reconstruct's outputs (BG_RR_LIMBS)."""
+    return (nprimes + 2) // 2
+
+
+def bg_fp_from_rational(p, num, den, out=None, status=None, stream=None):
+    """num / den mod p elementwise for int64 device tensors of one shape;
+    returns (out uint32 bits in int32, status uint8) of the same shape."""
+    import torch
+    if num.dtype != torch.int64 or den.dtype != torch.int64 or num.shape != den.shape:
+        raise TypeError("num and den must be int64 tensors of one shape")
+    if not (num.is_cuda and den.is_cuda and num.is_contiguous() and den.is_contiguous()):
+        raise TypeError("num and den must be contiguous HIP tensors")
+    if out is None:
+        out = torch.empty(num.shape, dtype=torch.int32, device=num.device)
+    if status is None:
+        status = torch.empty(num.shape, dtype=torch.uint8, device=num.device)
+    rc = lib().bg_fp_from_rational(ctypes.c_uint32(p), num.numel(), _ptr(num), _ptr(den), _ptr(out),
+                                   _ptr(status), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_fp_from_rational")
+    return out, status
+
+
+def bg_rational_reconstruct(primes, residues, npts=None, stream=None):
+    """Rationals from residues [nprimes][ld] (32-bit, one row per prime).
+    Returns (num int32 [L][npts] two's complement limbs, den int32 [L][npts]
+    holding uint32 limbs, status uint8 [npts]); L = bg_rr_limbs(nprimes)."""
+    import torch
+    k = len(primes)
+    if residues.dim() != 2 or residues.shape[0] != k or not residues.is_contiguous():
+        raise ValueError("residues must be a contiguous [nprimes][ld] tensor")
+    if residues.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        raise TypeError("residues must hold 32-bit values")
+    ld = residues.shape[1]
+    npts = ld if npts is None else int(npts)
+    L = bg_rr_limbs(k)
+    num = torch.zeros((L, max(ld, 1)), dtype=torch.int32, device=residues.device)
+    den = torch.zeros_like(num)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=residues.device)
+    parr = (ctypes.c_uint32 * max(k, 1))(*[int(p) for p in primes])
+    rc = lib().bg_rational_reconstruct(k, ctypes.cast(parr, ctypes.c_void_p), npts, ld, _ptr(residues), _ptr(num),
+                                       _ptr(den), _ptr(st), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_rational_reconstruct")
+    return num[:, :npts], den[:, :npts], st[:npts]
+
+
+def limbs_to_ints(limbs, signed: bool):
+    """Python ints from a host array of 32-bit limbs [L][npts] (least
+    significant first), two's complement when signed."""
+    import numpy as np
+    a = np.asarray(limbs).astype(np.uint32)
+    L = a.shape[0]
+    out = []
+    for q in range(a.shape[1]):
+        v = 0
+        for k in range(L - 1, -1, -1):
+            v = (v << 32) | int(a[k, q])
+        if signed and v >> (32 * L - 1):
+            v -= 1 << (32 * L)
+        out.append(v)
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -403,6 +403,69 @@ def generic_fp(seed: int, n: int, d: int, npts: int, p: int = DEFAULT_PRIME):
     return k.astype(np.uint32), eps.astype(np.uint32)
 
 
+def rational_points(seed: int, n: int, d: int, npts: int, kmax: int = 9, wmax: int = 5):
+    """Physical kinematic points with rational components (exact, Python
+    Fractions): n - 2 light-cone null momenta with integer k+ in [1, kmax]
+    and transverse components in [-kmax, kmax], a closing null pair
+    t r, Q - t r (Q = -sum of the others, r null, t = Q.Q / (2 Q.r)), one null
+    reference q per point and polarisations eps = w - (w.k)/(q.k) q with
+    integer w in [-wmax, wmax]; points with a vanishing sub-range P_S^2 are
+    redrawn.  Returns int64 numerator and denominator
+    arrays (knum, kden, enum, eden), each [npts][n][d]."""
+    from fractions import Fraction
+    import random
+    rng = random.Random(seed)
+
+    def dot(x, y):
+        return x[0] * y[0] - sum(a * b for a, b in zip(x[1:], y[1:]))
+
+    def null():
+        kp = Fraction(rng.randint(1, kmax))
+        kt = [Fraction(rng.randint(-kmax, kmax)) for _ in range(d - 2)]
+        km = sum(x * x for x in kt) / kp
+        return [(kp + km) / 2] + kt + [(kp - km) / 2]
+
+    out = np.zeros((4, npts, n, d), np.int64)
+    q = 0
+    while q < npts:
+        ks = [null() for _ in range(n - 2)]
+        Qv = [-sum(v[mu] for v in ks) for mu in range(d)]
+        r = null()
+        qr = dot(Qv, r)
+        if qr == 0:
+            continue
+        t = dot(Qv, Qv) / (2 * qr)
+        ks += [[t * x for x in r], [a - t * b for a, b in zip(Qv, r)]]
+        ref = null()
+        if any(dot(ref, v) == 0 for v in ks):
+            continue
+        # no vanishing propagator: P_S^2 != 0 for the contiguous S of legs 1..n-1, 2 <= |S| <= n-2
+        sing = False
+        for i in range(n - 1):
+            P = list(ks[i])
+            for j in range(i + 1, n - 1):
+                P = [a + b for a, b in zip(P, ks[j])]
+                if j - i + 1 <= n - 2 and dot(P, P) == 0:
+                    sing = True
+        if sing:
+            continue
+        eps = []
+        for v in ks:
+            w = [Fraction(rng.randint(-wmax, wmax)) for _ in range(d)]
+            c = dot(w, v) / dot(ref, v)
+            eps.append([a - c * b for a, b in zip(w, ref)])
+        vals = [ks, eps]
+        if any(abs(x.numerator) >= 2 ** 62 or x.denominator >= 2 ** 62 for vs in vals for v in vs for x in v):
+            continue
+        for s, vs in enumerate(vals):
+            for l in range(n):
+                for mu in range(d):
+                    out[2 * s, q, l, mu] = vs[l][mu].numerator
+                    out[2 * s + 1, q, l, mu] = vs[l][mu].denominator
+        q += 1
+    return out[0], out[1], out[2], out[3]
+
+
 def config_workload(name: str, npts: int | None = None):
     """The named synthetic workloads:
 

@@ -164,3 +164,34 @@ def test_metric_argument_checks():
         metric, n, d, npts, ld, m, D, D, NULL, NULL)
     assert c(metric=7) == bg.BG_EINVAL and c(d=0) == bg.BG_EDOMAIN and c(ld=3) == bg.BG_EINVAL
     assert c(npts=0, ld=0, m=NULL) == bg.BG_OK
+
+
+def test_rational_argument_checks():
+    """bg_fp_from_rational / bg_rational_reconstruct: prime checks, prime
+    count, duplicates, pointers; zero points is a no-op."""
+    L = bg.lib()
+    D = ctypes.c_void_p(0x1000)
+    assert L.bg_fp_from_rational(ctypes.c_uint32(2147483631), 4, D, D, D, NULL, NULL) == bg.BG_ENOTPRIME
+    assert L.bg_fp_from_rational(ctypes.c_uint32(2147483629), -1, D, D, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_fp_from_rational(ctypes.c_uint32(2147483629), 4, NULL, D, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_fp_from_rational(ctypes.c_uint32(2147483629), 0, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
+
+    def rr(primes, npts=10, ld=10, res=D, num=D, den=D):
+        arr = (ctypes.c_uint32 * max(len(primes), 1))(*primes)
+        return L.bg_rational_reconstruct(len(primes), ctypes.cast(arr, ctypes.c_void_p), npts, ld, res, num, den,
+                                         NULL, NULL)
+    good = [2147483629, 2147483587]
+    assert rr([]) == bg.BG_EINVAL
+    assert rr([2147483629] * 33) == bg.BG_EINVAL
+    assert rr([2147483629, 2147483629]) == bg.BG_EINVAL          # not distinct
+    assert rr([2147483629, 2147483631]) == bg.BG_ENOTPRIME
+    assert rr(good, ld=5) == bg.BG_EINVAL and rr(good, res=NULL) == bg.BG_EINVAL
+    assert rr(good, npts=0, ld=0, res=NULL, num=NULL, den=NULL) == bg.BG_OK
+    assert bg.bg_rr_limbs(1) == 1 and bg.bg_rr_limbs(8) == 5 and bg.bg_rr_limbs(32) == 17
+
+
+def test_limbs_to_ints():
+    import numpy as np
+    a = np.array([[0xFFFFFFFF, 5, 0], [0xFFFFFFFF, 0, 1]], dtype=np.uint32)
+    assert bg.limbs_to_ints(a, signed=True) == [-1, 5, 1 << 32]
+    assert bg.limbs_to_ints(a, signed=False) == [(1 << 64) - 1, 5, 1 << 32]

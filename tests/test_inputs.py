@@ -105,3 +105,19 @@ def test_workloads_are_seeded():
     assert np.array_equal(a["k"], b["k"]) and np.array_equal(a["eps"], b["eps"])
     c = I.config_workload("c5_small", npts=32)
     assert c["k"].shape == (32, 5, 4) and np.all(c["hel"][:, :2] == -1)
+
+
+def test_rational_points_are_physical():
+    """rational_points: massless momenta summing to zero and transverse
+    polarisations, exactly (fractions rebuilt from the int64 arrays)."""
+    from fractions import Fraction
+    n, d = 6, 5
+    kn, kd, en, ed = I.rational_points(3, n, d, 4)
+    dot = lambda x, y: x[0] * y[0] - sum(a * b for a, b in zip(x[1:], y[1:]))
+    for q in range(4):
+        k = [[Fraction(int(kn[q, l, m]), int(kd[q, l, m])) for m in range(d)] for l in range(n)]
+        e = [[Fraction(int(en[q, l, m]), int(ed[q, l, m])) for m in range(d)] for l in range(n)]
+        assert all(dot(v, v) == 0 for v in k)
+        assert all(sum(v[m] for v in k) == 0 for m in range(d))
+        assert all(dot(a, b) == 0 for a, b in zip(k, e))
+        assert (kd[q] > 0).all() and (ed[q] > 0).all()
