@@ -21,6 +21,7 @@ states        the d-dimensional polarisation states of paper Sec. 2.3 and
               their duals (square-root-free normalisation).
 rational      residues of rationals, Chinese remaindering and rational
               reconstruction (F_p samples back to Q).
+ffops         standalone batched F_p contractions and division.
 
 Parity status per function is stated in each module header.
 """
