@@ -269,6 +269,45 @@ def run_rational(steps: int, warmup: int, n: int = 5, d: int = 4, npts: int = 1 
 
 
 # ----------------------------------------------------------------------------
+# standalone Z_p operations (contraction and division)
+# ----------------------------------------------------------------------------
+
+def run_ffops(steps: int, warmup: int, npts: int = 1 << 20, dim: int = 6, ndiv: int = 1 << 24):
+    """bg_fp_contract with I = J = K = dim, second operand per event, over npts
+    events; bg_fp_divide over ndiv values.  HBM rooflines on the algorithmic
+    bytes (each input read once, each output written once)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    p = I.DEFAULT_PRIME
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(12)
+    rnd = lambda *shape: torch.randint(0, p, shape, generator=g, device=dev, dtype=torch.int64).to(torch.int32)
+    x, y = rnd(dim, dim, npts), rnd(dim, dim, npts)
+    box = {}
+    _, c_ms, _ = time_launches(lambda: box.__setitem__("c", bg.bg_fp_contract(p, x, y)), steps, warmup)
+    dx, dy = rnd(ndiv), rnd(ndiv)
+    _, d_ms, _ = time_launches(lambda: box.__setitem__("d", bg.bg_fp_divide(p, dx, dy)), steps, warmup)
+    c_bytes = npts * (3 * dim * dim * 4 + 1)
+    d_bytes = ndiv * (3 * 4 + 1)
+    roof = lambda b, ms: {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_TBS * 1e3,
+                          "unit": "GB/s", "frac": b / (ms * 1e-3) / (HBM_PEAK_TBS * 1e12)}
+    bad = int((box["c"][1] != 0).sum().item()) + int((box["d"][1] != 0).sum().item())
+    return {
+        "contract": {"workload": f"z = x y per event, {dim}x{dim} times {dim}x{dim}, {npts} events, Z_p p=2^31-19",
+                     "kernel_ms": c_ms, "value": npts / (c_ms * 1e-3), "unit": "events/s",
+                     "roofline": roof(c_bytes, c_ms)},
+        "divide": {"workload": f"z = x / y elementwise, {ndiv} values", "kernel_ms": d_ms,
+                   "value": ndiv / (d_ms * 1e-3), "unit": "values/s", "roofline": roof(d_bytes, d_ms)},
+        "nonzero_status": bad,
+    }
+
+
+# ----------------------------------------------------------------------------
 # polarisation states (d-dimensional states and duals of Sec. 2.3)
 # ----------------------------------------------------------------------------
 
@@ -586,7 +625,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational"],
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational", "ffops"],
                     default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -611,6 +650,9 @@ def main(argv=None):
         return
     if a.workload == "rational":
         print(json.dumps(run_rational(a.steps, a.warmup)), flush=True)
+        return
+    if a.workload == "ffops":
+        print(json.dumps(run_ffops(a.steps, a.warmup)), flush=True)
         return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
@@ -657,6 +699,7 @@ def main(argv=None):
     }
     line["states"] = run_states(a.steps, a.warmup)
     line["rational"] = run_rational(a.steps, a.warmup)
+    line["ffops"] = run_ffops(a.steps, a.warmup)
     if not a.no_batched:
         line["batched"] = run_batched(a.steps, a.warmup)
     if not a.no_served:

@@ -223,6 +223,42 @@ int bg_rational_reconstruct(int nprimes, const uint32_t* primes, int64_t npts, i
                             uint8_t* status, void* hip_stream);
 
 /*
+ * Standalone batched Z_p operations (paper Sec. 3: the finite-field library
+ * under the recursion, usable on its own).  Residues are canonical uint32 in
+ * [0, p), p an odd prime below 2^31 (BG_ENOTPRIME otherwise); element e of
+ * event q is at e * ld + q (the event index fastest).
+ *
+ * bg_fp_contract -- z[i][k] = sum_j x[i][j] y[j][k] mod p for every event:
+ *   I, J, K  1 .. BG_FP_MAX_DIM (BG_EDOMAIN otherwise); each of i, j, k
+ *            stands for any group of tensor indices, flattened by the caller
+ *            (e.g. z_{n i}^{k} = x_{n i j l} y_n^{j l k} has J = dim(j) dim(l))
+ *   x        device uint32 [I][J][ld]
+ *   y        device uint32 [J][K][ld] when y_batched != 0 (one y per event),
+ *            else [J][K] (one y shared by every event)
+ *   z        device uint32 [I][K][ld]
+ *   status   device uint8 [npts] or NULL: BG_PT_OK, or BG_PT_BADRESIDUE when
+ *            an input of the event is >= p (then every z of the event is
+ *            0xFFFFFFFF)
+ *
+ * bg_fp_divide -- z[q] = x[q] / y[q] mod p elementwise (count values):
+ *   x, y, z  device uint32 [count]
+ *   status   device uint8 [count] or NULL: BG_PT_OK; BG_PT_SINGULAR when
+ *            y[q] = 0; BG_PT_BADRESIDUE when x[q] or y[q] >= p; z[q] is
+ *            0xFFFFFFFF unless the status is BG_PT_OK
+ * bg_fp_divide_scalar -- the same with one y for every value (host
+ *            argument; BG_EDOMAIN when y = 0, BG_EINVAL when y >= p).
+ * All three are asynchronous on hip_stream and allocate nothing.
+ */
+#define BG_FP_MAX_DIM 4096
+int bg_fp_contract(uint32_t p, int I, int J, int K, int64_t npts, int64_t ld,
+                   const uint32_t* x, const uint32_t* y, int y_batched, uint32_t* z,
+                   uint8_t* status, void* hip_stream);
+int bg_fp_divide(uint32_t p, int64_t count, const uint32_t* x, const uint32_t* y,
+                 uint32_t* z, uint8_t* status, void* hip_stream);
+int bg_fp_divide_scalar(uint32_t p, int64_t count, const uint32_t* x, uint32_t y,
+                        uint32_t* z, uint8_t* status, void* hip_stream);
+
+/*
  * Batched form: many (field, n, d) groups in one call.  Each group has the
  * layout and meaning of one bg_amplitudes_* call; every group is validated
  * before anything is enqueued (the first invalid group's error is returned).

@@ -46,6 +46,13 @@ _SIGNATURES = {
     "bg_rational_reconstruct": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p]),
+    "bg_fp_contract": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_fp_divide": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_fp_divide_scalar": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bg_states_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -380,6 +387,67 @@ def limbs_to_ints(limbs, signed: bool):
             v -= 1 << (32 * L)
         out.append(v)
     return out
+
+
+# ----------------------------------------------------------------------------
+# standalone Z_p operations
+# ----------------------------------------------------------------------------
+
+BG_FP_MAX_DIM = 4096
+
+
+def _u32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous HIP tensor")
+    if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        raise TypeError(f"{name} must hold 32-bit residues")
+
+
+def bg_fp_contract(p, x, y, y_batched=True, npts=None, stream=None):
+    """z[i][k][q] = sum_j x[i][j][q] y[j][k](q) mod p.  x: [I][J][ld];
+    y: [J][K][ld] (batched) or [J][K] (shared).  Returns (z [I][K][ld], status [npts])."""
+    import torch
+    _u32(x, "x")
+    _u32(y, "y")
+    I, J, ld = x.shape
+    if y_batched:
+        if y.dim() != 3 or y.shape[0] != J or y.shape[2] != ld:
+            raise ValueError("y must be [J][K][ld]")
+    elif y.dim() != 2 or y.shape[0] != J:
+        raise ValueError("y must be [J][K]")
+    K = y.shape[1]
+    npts = ld if npts is None else int(npts)
+    z = torch.empty((I, K, ld), dtype=x.dtype, device=x.device)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=x.device)
+    rc = lib().bg_fp_contract(ctypes.c_uint32(p), I, J, K, npts, ld, _ptr(x), _ptr(y), 1 if y_batched else 0,
+                              _ptr(z), _ptr(st), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_fp_contract")
+    return z, st[:npts]
+
+
+def bg_fp_divide(p, x, y, stream=None):
+    """Elementwise x / y mod p (y a tensor of x's shape, or a Python int);
+    returns (z, status) of x's shape."""
+    import torch
+    _u32(x, "x")
+    z = torch.empty_like(x)
+    st = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    if isinstance(y, int):
+        rc = lib().bg_fp_divide_scalar(ctypes.c_uint32(p), x.numel(), _ptr(x), ctypes.c_uint32(y), _ptr(z),
+                                       _ptr(st), _stream_ptr(stream))
+        name = "bg_fp_divide_scalar"
+    else:
+        _u32(y, "y")
+        if y.shape != x.shape:
+            raise ValueError("x and y must have one shape")
+        rc = lib().bg_fp_divide(ctypes.c_uint32(p), x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(st),
+                                _stream_ptr(stream))
+        name = "bg_fp_divide"
+    if rc != BG_OK:
+        raise BGError(rc, name)
+    return z, st
 
 
 # ----------------------------------------------------------------------------

@@ -195,3 +195,19 @@ def test_limbs_to_ints():
     a = np.array([[0xFFFFFFFF, 5, 0], [0xFFFFFFFF, 0, 1]], dtype=np.uint32)
     assert bg.limbs_to_ints(a, signed=True) == [-1, 5, 1 << 32]
     assert bg.limbs_to_ints(a, signed=False) == [(1 << 64) - 1, 5, 1 << 32]
+
+
+def test_ffops_argument_checks():
+    L = bg.lib()
+    D = ctypes.c_void_p(0x1000)
+    c = lambda p=2147483629, I=2, J=3, K=4, npts=10, ld=10, x=D, y=D, z=D: L.bg_fp_contract(
+        ctypes.c_uint32(p), I, J, K, npts, ld, x, y, 1, z, NULL, NULL)
+    assert c(p=2147483631) == bg.BG_ENOTPRIME
+    assert c(I=0) == bg.BG_EDOMAIN and c(K=bg.BG_FP_MAX_DIM + 1) == bg.BG_EDOMAIN
+    assert c(ld=3) == bg.BG_EINVAL and c(y=NULL) == bg.BG_EINVAL and c(npts=-1) == bg.BG_EINVAL
+    assert c(npts=0, ld=0, x=NULL, y=NULL, z=NULL) == bg.BG_OK
+    P = ctypes.c_uint32(2147483629)
+    assert L.bg_fp_divide(P, 4, D, NULL, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_fp_divide(P, 0, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
+    assert L.bg_fp_divide_scalar(P, 4, D, ctypes.c_uint32(0), D, NULL, NULL) == bg.BG_EDOMAIN
+    assert L.bg_fp_divide_scalar(P, 4, D, ctypes.c_uint32(2147483629), D, NULL, NULL) == bg.BG_EINVAL
