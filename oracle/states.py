@@ -42,12 +42,18 @@ lamt, and the four-vector of a rank-one matrix u w^T is
 ((M11 + M22)/2, (M12 + M21)/2, i (M12 - M21)/2, (M11 - M22)/2), so that
 <a|gamma|b] = 2 vec(lam_a lamt_b^T).
 
+State sum of a cut leg (Sec. 2.1, the leading pole of the cut equation):
+with K_L, K_R the root currents of two trees whose last leg is the cut leg,
+    S = sum_s (e_s . K_L)(e~_s . K_R).
+
 Status: 0 ok; 1 singular (chi.k4 = 0, a zero bracket, an all-zero spinor
 chart, or a zero mu^2 product needed by d >= 5).
 
 Parity: pinned by tests/test_oracle_states.py (transversality,
 orthonormality and the completeness relation exactly over F_p and Q(i), the
-d = 4 states against Parke-Taylor through the amplitude oracle).
+d = 4 states against Parke-Taylor through the amplitude oracle; the state
+sum against the closed form the completeness relation gives, and against the
+sum of products of amplitudes with the states as polarisations).
 """
 from __future__ import annotations
 
@@ -146,3 +152,11 @@ def states(F, k, chi, i_unit):
         return 0, eps, epst
     except ZeroDivisionError:
         return 1, None, None
+
+
+def state_sum(F, KL, KR, eps, epst):
+    """sum_s (e_s . K_L)(e~_s . K_R), mostly-minus products."""
+    s = F.zero
+    for e, et in zip(eps, epst):
+        s = F.add(s, F.mul(mdot(F, e, KL), mdot(F, et, KR)))
+    return s

@@ -158,3 +158,48 @@ def test_singular_reference():
     rng = random.Random(9)
     k = null_fp(rng, 4)
     assert S.states(F, k, list(k), I_P)[0] == 1
+
+
+@pytest.mark.parametrize("d", [4, 5, 6, 8, 10])
+def test_state_sum_closed_form(d):
+    """The completeness relation turns the state sum into
+    -K_L.K_R + ((K_L.k)(eta.K_R) + (K_L.eta)(k.K_R)) / (k.eta) for any K_L, K_R."""
+    F = fields.Fp(P)
+    rng = random.Random(500 + d)
+    for _ in range(5):
+        k, chi = null_fp(rng, d), null_fp(rng, 4)
+        st, eps, epst = S.states(F, k, chi, I_P)
+        assert st == 0
+        KL = [rng.randrange(P) for _ in range(d)]
+        KR = [rng.randrange(P) for _ in range(d)]
+        eta = list(k[:4]) + [F.neg(x) for x in k[4:]] if d >= 5 else list(chi[:4])
+        ke = mdot(F, k, eta)
+        want = F.add(F.neg(mdot(F, KL, KR)),
+                     F.mul(F.add(F.mul(mdot(F, KL, k), mdot(F, eta, KR)), F.mul(mdot(F, KL, eta), mdot(F, k, KR))),
+                           F.inv(ke)))
+        assert S.state_sum(F, KL, KR, eps, epst) == want
+
+
+@pytest.mark.parametrize("nl,nr,d", [(4, 4, 4), (4, 5, 6), (5, 4, 7)])
+def test_state_sum_equals_sum_of_amplitude_products(nl, nr, d):
+    """With K_L, K_R the root currents of two trees whose last leg is the cut
+    leg (l and -l), the state sum equals sum_s M_L(.., e_s) M_R(.., e~_s)
+    evaluated with the amplitude oracle (the multilinearity in eps_n)."""
+    F = fields.Fp(P)
+    rng = random.Random(600 + nl + 10 * nr + d)
+    l = null_fp(rng, d)                    # the other momenta are arbitrary: the identity is algebraic
+    kl_ = [[rng.randrange(P) for _ in range(d)] for _ in range(nl - 1)] + [l]
+    kr_ = [[rng.randrange(P) for _ in range(d)] for _ in range(nr - 1)] + [[(-x) % P for x in l]]
+    el = [[rng.randrange(P) for _ in range(d)] for _ in range(nl)]
+    er = [[rng.randrange(P) for _ in range(d)] for _ in range(nr)]
+    st, eps, epst = S.states(F, l, null_fp(rng, 4), I_P)
+    assert st == 0
+    s1, _, KL = obg.currents(F, kl_, el)
+    s2, _, KR = obg.currents(F, kr_, er)
+    assert s1 == s2 == 0
+    total = F.zero
+    for e, et in zip(eps, epst):
+        a1 = obg.amplitude(F, kl_, el[:-1] + [e])[1]
+        a2 = obg.amplitude(F, kr_, er[:-1] + [et])[1]
+        total = F.add(total, F.mul(a1, a2))
+    assert S.state_sum(F, KL, KR, eps, epst) == total
