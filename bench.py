@@ -259,12 +259,76 @@ def run_rational(steps: int, warmup: int, n: int = 5, d: int = 4, npts: int = 1 
     return {
         "workload": f"n={n}, d={d} rational kinematic points (light-cone integers in [-9, 9], exact closing pair, "
                     f"integer w in [-5, 5]; {pool} distinct points tiled to {npts}), {nprimes} primes below 2^31",
-        "value": npts / (total_ms * 1e-3), "unit": "rational amplitudes/s",
+        "value": npts * steps / (total_ms * 1e-3), "unit": "rational amplitudes/s",
         "ms_per_step": total_ms / steps, "ms_residues_and_fp_amplitudes": fa_ms, "ms_reconstruct": rr_ms,
         "reconstruct": {"bound": "hbm", "achieved": rr_bytes / (rr_ms * 1e-3) / 1e9, "peak": HBM_PEAK_TBS * 1e3,
                         "unit": "GB/s", "frac": rr_bytes / (rr_ms * 1e-3) / (HBM_PEAK_TBS * 1e12),
                         "points_per_s": npts / (rr_ms * 1e-3)},
         "nonzero_status": bad, "npts": npts, "nprimes": nprimes,
+    }
+
+
+# ----------------------------------------------------------------------------
+# one-leg cut: states of the cut leg, two root currents, the state sum
+# ----------------------------------------------------------------------------
+
+def run_cut(steps: int, warmup: int, n: int = 6, d: int = 6, npts: int = 1 << 20):
+    """sum_s M_L(.., e_s) M_R(.., e~_s) over Z_p for two n-point trees joined
+    by a cut leg l: bg_states_fp (l), bg_currents_fp (both trees),
+    bg_state_sum_fp; random residues for the other legs (the identities are
+    algebraic), inputs resident."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    p = I.DEFAULT_PRIME
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(21)
+    l = I.fp_null(rng, p, (npts,), d).astype(np.uint32)
+    chi = I.fp_null(rng, p, (npts,), 4).astype(np.uint32)
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+    tl, tchi = up(l.T), up(chi.T)
+    g = torch.Generator(device=dev)
+    g.manual_seed(22)
+    rnd = lambda *shape: torch.randint(0, p, shape, generator=g, device=dev, dtype=torch.int64).to(torch.int32)
+    kL, kR, eL, eR = rnd(n, d, npts), rnd(n, d, npts), rnd(n, d, npts), rnd(n, d, npts)
+    kL[n - 1].copy_(tl)
+    kR[n - 1].copy_(torch.remainder(p - tl.to(torch.int64).bitwise_and(0xFFFFFFFF), p).to(torch.int32))
+    bg.bg_autotune(bg.BG_FIELD_FP, n, d, p, npts=npts, reps=3)
+    box = {}
+
+    def states():
+        box["s"] = bg.bg_states_fp(tl, tchi, p)
+
+    def currents():
+        box["L"] = bg.bg_currents_fp(kL, eL, p)
+        box["R"] = bg.bg_currents_fp(kR, eR, p)
+
+    def ssum():
+        e, et, _ = box["s"]
+        box["S"] = bg.bg_state_sum(box["L"][0], box["R"][0], e, et, p=p)
+
+    def whole():
+        states()
+        currents()
+        ssum()
+
+    total_ms, _, _ = time_launches(whole, steps, warmup)
+    _, st_ms, _ = time_launches(states, steps, warmup)
+    _, cu_ms, _ = time_launches(currents, steps, warmup)
+    _, ss_ms, _ = time_launches(ssum, steps, warmup)
+    bad = int((box["S"][1] != 0).sum().item()) + int((box["L"][1] != 0).sum().item())
+    ss_bytes = npts * 4 * (2 * d + 2 * (d - 2) * d + 1) + npts
+    return {
+        "workload": f"two {n}-point trees joined by one cut leg, d={d}, Z_p p=2^31-19, {npts} points",
+        "value": npts * steps / (total_ms * 1e-3), "unit": "state-summed cut products/s",
+        "ms_per_step": total_ms / steps, "ms_states": st_ms, "ms_two_root_currents": cu_ms, "ms_state_sum": ss_ms,
+        "state_sum_roofline": {"bound": "hbm", "achieved": ss_bytes / (ss_ms * 1e-3) / 1e9,
+                               "peak": HBM_PEAK_TBS * 1e3, "unit": "GB/s",
+                               "frac": ss_bytes / (ss_ms * 1e-3) / (HBM_PEAK_TBS * 1e12)},
+        "nonzero_status": bad,
     }
 
 
@@ -625,7 +689,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational", "ffops"],
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational", "ffops", "cut"],
                     default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -653,6 +717,9 @@ def main(argv=None):
         return
     if a.workload == "ffops":
         print(json.dumps(run_ffops(a.steps, a.warmup)), flush=True)
+        return
+    if a.workload == "cut":
+        print(json.dumps(run_cut(a.steps, a.warmup)), flush=True)
         return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
@@ -700,6 +767,7 @@ def main(argv=None):
     line["states"] = run_states(a.steps, a.warmup)
     line["rational"] = run_rational(a.steps, a.warmup)
     line["ffops"] = run_ffops(a.steps, a.warmup)
+    line["cut"] = run_cut(a.steps, a.warmup)
     if not a.no_batched:
         line["batched"] = run_batched(a.steps, a.warmup)
     if not a.no_served:

@@ -114,6 +114,23 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p,
                      uint32_t* out, uint8_t* status, void* hip_stream);
 
 /*
+ * bg_currents_c128, bg_currents_fp -- the root current K([1..n-1]) instead
+ * of M (paper Sec. 2.2: the amplitude is the contraction of the current of
+ * legs 1..n-1, its propagator removed, with eps_n): M = eps_n . K, so one
+ * call gives M for every polarisation of leg n.  Same arguments, layouts,
+ * statuses and errors as bg_amplitudes_*, except
+ *   cur      device [d][ld] (complex128, or uint32 residues in [0, p)):
+ *            component mu of point q at mu * ld + q; every component of a
+ *            point with a non-zero status holds the sentinel.
+ * pols row n-1 (eps_n) does not enter K but is read and must hold
+ * canonical residues over Z_p.  Mostly-minus metric.
+ */
+int bg_currents_c128(int n, int d, int64_t npts, int64_t ld, const double* momenta,
+                     const double* pols, double* cur, uint8_t* status, void* hip_stream);
+int bg_currents_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
+                   const uint32_t* pols, uint32_t* cur, uint8_t* status, void* hip_stream);
+
+/*
  * Metric of every Minkowski product (propagators P^2 and all contractions).
  *   BG_METRIC_MOSTLY_MINUS  diag(1, -1, ..., -1)           (paper Sec. 2.2; the
  *                           metric of bg_amplitudes_c128 / _fp and of every
@@ -175,6 +192,29 @@ int bg_states_c128(int d, int64_t npts, int64_t ld, const double* momenta, const
 int bg_states_fp(int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
                  const uint32_t* chi, uint32_t* eps, uint32_t* epst, uint8_t* status,
                  void* hip_stream);
+
+/*
+ * bg_state_sum_c128, bg_state_sum_fp -- sum over the states of one cut leg
+ * of a product of two trees (paper Sec. 2.1, the leading pole of the cut
+ * equation, with the states of Sec. 2.3):
+ *   S[q] = sum_{s < d-2} (e_s . K_L)(e~_s . K_R)     (mostly-minus products)
+ * where K_L, K_R are root currents (bg_currents_*) of two trees whose last
+ * leg is the cut leg (momentum l in one, -l in the other) and e_s, e~_s the
+ * states and duals of l (bg_states_*), so that M_L(e_s) = e_s . K_L and
+ * M_R(e~_s) = e~_s . K_R.
+ *   d        4 <= d <= BG_MAX_D (BG_EDOMAIN otherwise)
+ *   kl, kr   device [d][ld]; eps, epst device [d-2][d][ld] (as bg_states_*)
+ *   out      device [npts] (complex128, or uint32 in [0, p))
+ *   status   device uint8 [npts] or NULL: BG_PT_OK; over Z_p BG_PT_BADRESIDUE
+ *            when an input is >= p (e.g. a sentinel; out is 0xFFFFFFFF);
+ *            over C BG_PT_SINGULAR when the result is not a number.
+ */
+int bg_state_sum_c128(int d, int64_t npts, int64_t ld, const double* kl, const double* kr,
+                      const double* eps, const double* epst, double* out, uint8_t* status,
+                      void* hip_stream);
+int bg_state_sum_fp(int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* kl,
+                    const uint32_t* kr, const uint32_t* eps, const uint32_t* epst, uint32_t* out,
+                    uint8_t* status, void* hip_stream);
 
 /*
  * From Z_p samples back to rational numbers (paper Sec. 1 and Sec. 3: values

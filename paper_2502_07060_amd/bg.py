@@ -53,6 +53,18 @@ _SIGNATURES = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bg_fp_divide_scalar": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_currents_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "bg_currents_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "bg_state_sum_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "bg_state_sum_fp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bg_states_c128": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -315,6 +327,68 @@ def bg_states_fp(momenta, chi, p, npts=None, stream=None):
     if rc != BG_OK:
         raise BGError(rc, "bg_states_fp")
     return eps[..., :npts], epst[..., :npts], st[:npts]
+
+
+# ----------------------------------------------------------------------------
+# root currents and sums over the states of a cut leg
+# ----------------------------------------------------------------------------
+
+def bg_currents_c128(momenta, pols, npts=None, stream=None):
+    """Root currents K([1..n-1]) over complex128: returns (cur [d][ld], status [npts])."""
+    import torch
+    n, d = momenta.shape[0], momenta.shape[1]
+    ld = _check_soa("momenta", momenta, n, d, torch.complex128)
+    if _check_soa("pols", pols, n, d, torch.complex128) != ld:
+        raise ValueError("momenta and pols must share ld")
+    npts = ld if npts is None else int(npts)
+    cur = torch.empty((d, ld), dtype=torch.complex128, device=momenta.device)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=momenta.device)
+    rc = lib().bg_currents_c128(n, d, npts, ld, _ptr(momenta), _ptr(pols), _ptr(cur), _ptr(st), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_currents_c128")
+    return cur, st[:npts]
+
+
+def bg_currents_fp(momenta, pols, p, npts=None, stream=None):
+    """Root currents K([1..n-1]) mod p: returns (cur [d][ld] 32-bit, status [npts])."""
+    import torch
+    n, d = momenta.shape[0], momenta.shape[1]
+    dt = momenta.dtype
+    ld = _check_soa("momenta", momenta, n, d, dt)
+    if _check_soa("pols", pols, n, d, dt) != ld:
+        raise ValueError("momenta and pols must share ld")
+    npts = ld if npts is None else int(npts)
+    cur = torch.empty((d, ld), dtype=dt, device=momenta.device)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=momenta.device)
+    rc = lib().bg_currents_fp(n, d, npts, ld, ctypes.c_uint32(p), _ptr(momenta), _ptr(pols), _ptr(cur), _ptr(st),
+                              _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_currents_fp")
+    return cur, st[:npts]
+
+
+def bg_state_sum(kl, kr, eps, epst, p=None, npts=None, stream=None):
+    """sum_s (e_s . K_L)(e~_s . K_R) per point: kl, kr [d][ld]; eps, epst
+    [d-2][d][ld] (complex128, or 32-bit residues with prime p)."""
+    import torch
+    d, ld = kl.shape
+    npts = ld if npts is None else int(npts)
+    for name, t in (("kl", kl), ("kr", kr), ("eps", eps), ("epst", epst)):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != kl.dtype or t.shape[-1] != ld:
+            raise TypeError(f"{name}: contiguous HIP tensor of kl's dtype and ld")
+    out = torch.empty(max(ld, 1), dtype=kl.dtype, device=kl.device)
+    st = torch.empty(max(ld, 1), dtype=torch.uint8, device=kl.device)
+    if kl.dtype == torch.complex128:
+        rc = lib().bg_state_sum_c128(d, npts, ld, _ptr(kl), _ptr(kr), _ptr(eps), _ptr(epst), _ptr(out), _ptr(st),
+                                     _stream_ptr(stream))
+        name = "bg_state_sum_c128"
+    else:
+        rc = lib().bg_state_sum_fp(d, npts, ld, ctypes.c_uint32(p), _ptr(kl), _ptr(kr), _ptr(eps), _ptr(epst),
+                                   _ptr(out), _ptr(st), _stream_ptr(stream))
+        name = "bg_state_sum_fp"
+    if rc != BG_OK:
+        raise BGError(rc, name)
+    return out[:npts], st[:npts]
 
 
 # ----------------------------------------------------------------------------

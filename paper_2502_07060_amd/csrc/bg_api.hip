@@ -80,6 +80,8 @@ FpConst make_fp_const(uint32_t p) {
   // 2^-32 mod p = (2^32 mod p)^(p-2)
   const uint64_t inv32 = powmod(c32, p - 2, p);
   k.r4s = balanced((unsigned __int128)((unsigned __int128)R2 * R2 % p) * inv32 % p, p);
+  k.r3 = balanced((unsigned __int128)R2 * R % p, p);
+  k.r3s = balanced((unsigned __int128)((unsigned __int128)R2 * R % p) * inv32 % p, p);
   return k;
 }
 
@@ -211,6 +213,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.fp = fp;
   a.metric = BG_METRIC_MOSTLY_MINUS;
   a.ialt = 0;
+  a.cur = nullptr;
   spec.fn = v->fn;
   spec.generic = v->generic;
   spec.lanes = v->L;
@@ -331,6 +334,43 @@ int bg_amplitudes_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const u
                      const uint32_t* pols, uint32_t* out, uint8_t* status, void* hip_stream) {
   return bg_amplitudes_fp_metric(BG_METRIC_MOSTLY_MINUS, n, d, npts, ld, p, momenta, pols, out, status,
                                  hip_stream);
+}
+
+// root current K([1..n-1]) instead of M: same preparation, `cur` in place of `out`
+static int launch_currents(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta,
+                           const void* pols, void* cur, uint8_t* status, const bg::FpConst& fp,
+                           hipStream_t stream) {
+  bg::LaunchSpec spec;
+  const int rc = bg::prepare(field, n, d, npts, ld, momenta, pols, nullptr, status, fp, spec);
+  if (rc != BG_OK) return rc;
+  spec.args.cur = cur;
+  return bg::enqueue(spec, stream);
+}
+
+int bg_currents_c128(int n, int d, int64_t npts, int64_t ld, const double* momenta, const double* pols,
+                     double* cur, uint8_t* status, void* hip_stream) {
+  int rc = bg::check_common(n, d, npts, ld);
+  if (rc != BG_OK) return rc;
+  if (npts == 0) return BG_OK;
+  rc = bg::check_buffers(npts, ld, momenta, pols, cur);
+  if (rc != BG_OK) return rc;
+  bg::FpConst none;
+  memset(&none, 0, sizeof(none));
+  return launch_currents(bg::FIELD_C128, n, d, npts, ld, momenta, pols, cur, status, none,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+int bg_currents_fp(int n, int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* momenta,
+                   const uint32_t* pols, uint32_t* cur, uint8_t* status, void* hip_stream) {
+  int rc = bg::check_common(n, d, npts, ld);
+  if (rc != BG_OK) return rc;
+  if (p < 3 || p >= 0x80000000u || !bg::is_prime_u32(p)) return BG_ENOTPRIME;
+  if (npts == 0) return BG_OK;
+  rc = bg::check_buffers(npts, ld, momenta, pols, cur);
+  if (rc != BG_OK) return rc;
+  const bg::FpConst k = bg::make_fp_const(p);
+  return launch_currents(bg::FIELD_FP, n, d, npts, ld, momenta, pols, cur, status, k,
+                         static_cast<hipStream_t>(hip_stream));
 }
 
 int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {

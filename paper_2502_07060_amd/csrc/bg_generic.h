@@ -82,7 +82,7 @@ struct GenericRecursion {
   }
 
   __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad, bool& singular,
-                      S& result) {
+                      S& result, E (&kroot)[DMAX]) {
     const int nprop = Lay::nprop(N);
     if constexpr (kFp) {
 #pragma unroll
@@ -253,6 +253,8 @@ struct GenericRecursion {
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) Kf[c] = F.finish(K[c]);
           result = F.ndot_u(epsn, Kf);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) kroot[c] = Kf[c];
         }
       }
     }
@@ -293,35 +295,63 @@ __global__ __launch_bounds__(256) void bg_generic_kernel(LaunchArgs a, int N) {
   uint32_t bad = 0;
   bool singular = false;
   typename Fld::S res;
+  typename Fld::E kroot[DMAX];
   GenericRecursion<Fld, DMAX> G(lds, P, t, N);
   if constexpr (Fld::exact) {
     Fld F(a.fp, 0);
-    G.run(F, a, q, bad, singular, res);
+    G.run(F, a, q, bad, singular, res, kroot);
     bad = bad >= (uint32_t)a.fp.p ? 1u : 0u;
     if (valid) {
       uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
-      uint32_t outv = 0xFFFFFFFFu;
-      if (st == PT_OK) {
-        int32_t m = fp_mul(res, a.fp.r4, a.fp);
-        m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
-        outv = fp_to_canonical(m, a.fp);
+      if (a.cur) {
+        // root current K = 2 K', kroot scaled by R^-3: one product with R^3
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          if (c < a.d) {
+            uint32_t v = 0xFFFFFFFFu;
+            if (st == PT_OK) {
+              const int32_t m = fp_mul(kroot[c], a.fp.r3, a.fp);
+              v = fp_to_canonical(fp_add(m, m, a.fp), a.fp);
+            }
+            static_cast<uint32_t*>(a.cur)[(int64_t)c * a.ld + q] = v;
+          }
+        }
+      } else {
+        uint32_t outv = 0xFFFFFFFFu;
+        if (st == PT_OK) {
+          int32_t m = fp_mul(res, a.fp.r4, a.fp);
+          m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
+          outv = fp_to_canonical(m, a.fp);
+        }
+        static_cast<uint32_t*>(a.out)[q] = outv;
       }
-      static_cast<uint32_t*>(a.out)[q] = outv;
       if (a.status) a.status[q] = st;
     }
   } else {
     Fld F(0);
-    G.run(F, a, q, bad, singular, res);
+    G.run(F, a, q, bad, singular, res, kroot);
     if (valid) {
-      double2 o;
-      if (singular) {
-        o.x = __builtin_nan("");
-        o.y = __builtin_nan("");
+      if (a.cur) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          if (c < a.d) {
+            double2 o;
+            o.x = singular ? __builtin_nan("") : 2.0 * kroot[c].re;
+            o.y = singular ? __builtin_nan("") : 2.0 * kroot[c].im;
+            static_cast<double2*>(a.cur)[(int64_t)c * a.ld + q] = o;
+          }
+        }
       } else {
-        o.x = -2.0 * res.re;
-        o.y = -2.0 * res.im;
+        double2 o;
+        if (singular) {
+          o.x = __builtin_nan("");
+          o.y = __builtin_nan("");
+        } else {
+          o.x = -2.0 * res.re;
+          o.y = -2.0 * res.im;
+        }
+        static_cast<double2*>(a.out)[q] = o;
       }
-      static_cast<double2*>(a.out)[q] = o;
       if (a.status) a.status[q] = singular ? PT_SINGULAR : PT_OK;
     }
   }

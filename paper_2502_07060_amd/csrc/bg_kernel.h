@@ -55,6 +55,9 @@ struct LaunchArgs {
   // the mostly-minus one on load (see Loader)
   int metric;
   int32_t ialt;  // F_p, alternating metric: a square root of -1 times R (Montgomery form)
+  // root-current mode: when non-null, the kernels write K([1..n-1]) (d
+  // components, [d][ld]) here instead of M to `out`
+  void* cur;
 };
 
 // ---------------------------------------------------------------------------
@@ -217,7 +220,7 @@ struct Recursion {
 
   template <int BLOCK, bool ALT>
   __device__ static void run(const Fld& F, const LaunchArgs& a, int64_t q, int s, uint32_t& bad,
-                             bool& singular, S& result, Lds<BLOCK>* lds) {
+                             bool& singular, S& result, E (&kroot)[DL], Lds<BLOCK>* lds) {
     constexpr bool kFp = Fld::exact;
     E J[NCUR][DL];
     E epsn[DL];
@@ -432,6 +435,8 @@ struct Recursion {
 #pragma unroll
           for (int c = 0; c < DL; ++c) Kf[c] = F.finish(K[c]);
           result = F.ndot_u(epsn, Kf);
+#pragma unroll
+          for (int c = 0; c < DL; ++c) kroot[c] = Kf[c];
         }
       });
     });
@@ -514,16 +519,35 @@ void bg_recursion_kernel(LaunchArgs a) {
   uint32_t bad = 0;
   bool singular = false;
   typename Fld::S res;
+  typename Fld::E kroot[DL];
   if constexpr (Fld::exact) {
     Fld F(a.fp, s);
-    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, &lds);
-    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, &lds);
+    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, kroot, &lds);
+    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, kroot, &lds);
     if constexpr (L > 1)
       bad = group_sum<L>(bad, [](uint32_t x, uint32_t y) { return x > y ? x : y; },
                          [](auto ctrl, uint32_t v) { return dpp_u32<decltype(ctrl)::value>(v); });
     bad = bad >= (uint32_t)a.fp.p ? 1u : 0u;
-    if (valid && s == 0) {
-      uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
+    const uint8_t st = bad ? PT_BADRESIDUE : (singular ? PT_SINGULAR : PT_OK);
+    if (a.cur) {
+      // root current K = 2 K'; kroot carries R^-3 (degree n - 1 in eps, 4 - n
+      // in k) and the accumulator's 2^32: one product with R^3 2^-32 restores it
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < DL; ++c) {
+          const int mu = s * DL + c;
+          if (mu < a.d) {
+            uint32_t v = 0xFFFFFFFFu;
+            if (st == PT_OK) {
+              const int32_t m = fp_mul(kroot[c], a.fp.r3s, a.fp);
+              v = fp_to_canonical(fp_add(m, m, a.fp), a.fp);
+            }
+            static_cast<uint32_t*>(a.cur)[(int64_t)mu * a.ld + q] = v;
+          }
+        }
+        if (a.status && s == 0) a.status[q] = st;
+      }
+    } else if (valid && s == 0) {
       uint32_t outv = 0xFFFFFFFFu;
       if (st == PT_OK) {
         // res = -(eps_n . K') in Montgomery form of a value scaled by R^-4,
@@ -538,9 +562,23 @@ void bg_recursion_kernel(LaunchArgs a) {
     }
   } else {
     Fld F(s);
-    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, &lds);
-    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, &lds);
-    if (valid && s == 0) {
+    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, kroot, &lds);
+    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, kroot, &lds);
+    if (a.cur) {
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < DL; ++c) {
+          const int mu = s * DL + c;
+          if (mu < a.d) {
+            double2 o;
+            o.x = singular ? __builtin_nan("") : 2.0 * kroot[c].re;
+            o.y = singular ? __builtin_nan("") : 2.0 * kroot[c].im;
+            static_cast<double2*>(a.cur)[(int64_t)mu * a.ld + q] = o;
+          }
+        }
+        if (a.status && s == 0) a.status[q] = singular ? PT_SINGULAR : PT_OK;
+      }
+    } else if (valid && s == 0) {
       double2 o;
       if (singular) {
         o.x = __builtin_nan("");

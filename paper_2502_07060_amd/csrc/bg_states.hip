@@ -406,10 +406,153 @@ int launch_states(bool fp, int d, int64_t npts, int64_t ld, uint32_t p, const vo
   return e == hipSuccess ? BG_OK : BG_EHIP;
 }
 
+// ---------------------------------------------------------------------------
+// sums over the states of one cut leg: S = sum_s (e_s . K_L)(e~_s . K_R)
+// ---------------------------------------------------------------------------
+// With K_L, K_R the root currents of two trees whose last leg is the cut leg
+// (momentum l in one, -l in the other), M_L(e_s) = e_s . K_L and
+// M_R(e~_s) = e~_s . K_R, so S is the state sum of their product (paper
+// Sec. 2.1, the leading pole of the cut equation; Sec. 2.3 states).  One
+// point per lane; mostly-minus products.
+struct StateSumArgs {
+  const void* kl;
+  const void* kr;
+  const void* eps;
+  const void* epst;
+  void* out;
+  uint8_t* status;
+  int64_t npts, ld;
+  int d;
+  FpConst fp;
+};
+
+__global__ __launch_bounds__(256) void state_sum_fp_kernel(StateSumArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.npts) return;
+  const FpConst& F = a.fp;
+  const uint32_t* kl = static_cast<const uint32_t*>(a.kl);
+  const uint32_t* kr = static_cast<const uint32_t*>(a.kr);
+  const uint32_t* ep = static_cast<const uint32_t*>(a.eps);
+  const uint32_t* et = static_cast<const uint32_t*>(a.epst);
+  uint32_t maxraw = 0;
+  auto rd = [&](const uint32_t* base, int64_t e) {
+    const uint32_t v = base[e * a.ld + q];
+    maxraw = maxraw > v ? maxraw : v;
+    return fp_from_canonical(v < (uint32_t)F.p ? v : 0u, F);
+  };
+  int32_t L[BG_MAX_D], Rv[BG_MAX_D];
+#pragma unroll
+  for (int mu = 0; mu < BG_MAX_D; ++mu) {
+    L[mu] = mu < a.d ? rd(kl, mu) : 0;
+    Rv[mu] = mu < a.d ? rd(kr, mu) : 0;
+  }
+  L[0] = -L[0];  // primed: sum_mu L'_mu x_mu = -(L . x)
+  Rv[0] = -Rv[0];
+  // (e.K_L)(e~.K_R) = (-(e.K_L))(-(e~.K_R)); each dot is an int64 sum of
+  // balanced products (a fold after every four), reduced to t R^-1; the
+  // products of two such are summed in int64 and reduced once more (R^-3),
+  // and one product with R^4 restores S
+  int64_t acc = 0;
+  for (int s = 0; s < a.d - 2; ++s) {
+    int64_t tl = 0, tr = 0;
+#pragma unroll
+    for (int mu = 0; mu < BG_MAX_D; ++mu) {
+      if (mu < a.d) {
+        tl = mad64(rd(ep, (int64_t)s * a.d + mu), L[mu], tl);
+        tr = mad64(rd(et, (int64_t)s * a.d + mu), Rv[mu], tr);
+      }
+      if ((mu & 3) == 3) {
+        tl = fp_fold(tl, F);
+        tr = fp_fold(tr, F);
+      }
+    }
+    const int32_t dl = fp_redc2(fp_fold(tl, F), F), dr = fp_redc2(fp_fold(tr, F), F);
+    acc = fp_fold(mad64(dl, dr, acc), F);
+  }
+  const bool bad = maxraw >= (uint32_t)F.p;
+  const int32_t sum = fp_mul(fp_redc2(acc, F), F.r4, F);
+  static_cast<uint32_t*>(a.out)[q] = bad ? 0xFFFFFFFFu : fp_to_canonical(sum, F);
+  if (a.status) a.status[q] = bad ? PT_BADRESIDUE : PT_OK;
+}
+
+__global__ __launch_bounds__(256) void state_sum_c128_kernel(StateSumArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.npts) return;
+  const double2* kl = static_cast<const double2*>(a.kl);
+  const double2* kr = static_cast<const double2*>(a.kr);
+  const double2* ep = static_cast<const double2*>(a.eps);
+  const double2* et = static_cast<const double2*>(a.epst);
+  double2 L[BG_MAX_D], Rv[BG_MAX_D];
+  bool nan = false;
+#pragma unroll
+  for (int mu = 0; mu < BG_MAX_D; ++mu) {
+    L[mu] = mu < a.d ? kl[(int64_t)mu * a.ld + q] : double2{0.0, 0.0};
+    Rv[mu] = mu < a.d ? kr[(int64_t)mu * a.ld + q] : double2{0.0, 0.0};
+  }
+  double sre = 0.0, sim = 0.0;
+  for (int s = 0; s < a.d - 2; ++s) {
+    double lre = 0.0, lim = 0.0, rre = 0.0, rim = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < BG_MAX_D; ++mu) {
+      if (mu < a.d) {
+        const double g = mu == 0 ? 1.0 : -1.0;
+        const double2 e = ep[((int64_t)s * a.d + mu) * a.ld + q];
+        const double2 f = et[((int64_t)s * a.d + mu) * a.ld + q];
+        lre = __builtin_fma(g * e.x, L[mu].x, __builtin_fma(-g * e.y, L[mu].y, lre));
+        lim = __builtin_fma(g * e.x, L[mu].y, __builtin_fma(g * e.y, L[mu].x, lim));
+        rre = __builtin_fma(g * f.x, Rv[mu].x, __builtin_fma(-g * f.y, Rv[mu].y, rre));
+        rim = __builtin_fma(g * f.x, Rv[mu].y, __builtin_fma(g * f.y, Rv[mu].x, rim));
+      }
+    }
+    sre = __builtin_fma(lre, rre, __builtin_fma(-lim, rim, sre));
+    sim = __builtin_fma(lre, rim, __builtin_fma(lim, rre, sim));
+  }
+  nan = sre != sre || sim != sim;
+  static_cast<double2*>(a.out)[q] = double2{sre, sim};
+  if (a.status) a.status[q] = nan ? PT_SINGULAR : PT_OK;
+}
+
+int launch_state_sum(bool fp, int d, int64_t npts, int64_t ld, uint32_t p, const void* kl, const void* kr,
+                     const void* eps, const void* epst, void* out, uint8_t* status, void* stream) {
+  if (d < 4 || d > BG_MAX_D) return BG_EDOMAIN;
+  if (fp && (p < 3 || p >= 0x80000000u || !is_prime_u32(p))) return BG_ENOTPRIME;
+  if (npts < 0) return BG_EINVAL;
+  if (npts == 0) return BG_OK;
+  if (ld < npts || !kl || !kr || !eps || !epst || !out) return BG_EINVAL;
+  StateSumArgs a{};
+  a.kl = kl;
+  a.kr = kr;
+  a.eps = eps;
+  a.epst = epst;
+  a.out = out;
+  a.status = status;
+  a.npts = npts;
+  a.ld = ld;
+  a.d = d;
+  if (fp) a.fp = make_fp_const(p);
+  const int64_t blocks = (npts + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return BG_EINVAL;
+  void* args[] = {&a};
+  const hipError_t e = hipLaunchKernel(fp ? reinterpret_cast<const void*>(&state_sum_fp_kernel)
+                                          : reinterpret_cast<const void*>(&state_sum_c128_kernel),
+                                       dim3((unsigned)blocks), dim3(256), args, 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BG_OK : BG_EHIP;
+}
+
 }  // namespace
 }  // namespace bg
 
 extern "C" {
+
+int bg_state_sum_c128(int d, int64_t npts, int64_t ld, const double* kl, const double* kr, const double* eps,
+                      const double* epst, double* out, uint8_t* status, void* hip_stream) {
+  return bg::launch_state_sum(false, d, npts, ld, 0, kl, kr, eps, epst, out, status, hip_stream);
+}
+
+int bg_state_sum_fp(int d, int64_t npts, int64_t ld, uint32_t p, const uint32_t* kl, const uint32_t* kr,
+                    const uint32_t* eps, const uint32_t* epst, uint32_t* out, uint8_t* status, void* hip_stream) {
+  return bg::launch_state_sum(true, d, npts, ld, p, kl, kr, eps, epst, out, status, hip_stream);
+}
 
 int bg_states_c128(int d, int64_t npts, int64_t ld, const double* momenta, const double* chi, double* eps,
                    double* epst, uint8_t* status, void* hip_stream) {

@@ -368,7 +368,7 @@ struct WideRecursion {
     F.fold(K);
   }
 
-  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result) {
+  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result, E (&kroot)[DMAX]) {
     uint32_t bad = 0;
     bool singular = false;
     load(F, a, q, bad);
@@ -481,6 +481,8 @@ struct WideRecursion {
             en[c] = En[c];
           }
           result = F.ndot_u(en, Kf);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) kroot[c] = Kf[c];
         }
       }
       group_sync();
@@ -513,35 +515,63 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
   WideRecursion<Fld, DMAX, G, PAD> W(lds + (size_t)pb * Lay::offsets(N).total, N, g);
   typename Fld::S res;
+  typename Fld::E kroot[DMAX];
   if constexpr (Fld::exact) {
     Fld F(a.fp, 0);
-    W.run(F, a, q, res);
+    W.run(F, a, q, res, kroot);
     if (valid && g == 0) {
       const unsigned fl = *W.flags;
       const uint8_t st = (fl & 1u) ? PT_BADRESIDUE : ((fl & 2u) ? PT_SINGULAR : PT_OK);
-      uint32_t outv = 0xFFFFFFFFu;
-      if (st == PT_OK) {
-        int32_t m = fp_mul(res, a.fp.r4, a.fp);
-        m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
-        outv = fp_to_canonical(m, a.fp);
+      if (a.cur) {
+        // root current K = 2 K', kroot scaled by R^-3: one product with R^3
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          if (c < a.d) {
+            uint32_t v = 0xFFFFFFFFu;
+            if (st == PT_OK) {
+              const int32_t m = fp_mul(kroot[c], a.fp.r3, a.fp);
+              v = fp_to_canonical(fp_add(m, m, a.fp), a.fp);
+            }
+            static_cast<uint32_t*>(a.cur)[(int64_t)c * a.ld + q] = v;
+          }
+        }
+      } else {
+        uint32_t outv = 0xFFFFFFFFu;
+        if (st == PT_OK) {
+          int32_t m = fp_mul(res, a.fp.r4, a.fp);
+          m = fp_sub(0, fp_add(m, m, a.fp), a.fp);
+          outv = fp_to_canonical(m, a.fp);
+        }
+        static_cast<uint32_t*>(a.out)[q] = outv;
       }
-      static_cast<uint32_t*>(a.out)[q] = outv;
       if (a.status) a.status[q] = st;
     }
   } else {
     Fld F(0);
-    W.run(F, a, q, res);
+    W.run(F, a, q, res, kroot);
     if (valid && g == 0) {
       const bool sing = (*W.flags & 2u) != 0;
-      double2 o;
-      if (sing) {
-        o.x = __builtin_nan("");
-        o.y = __builtin_nan("");
+      if (a.cur) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          if (c < a.d) {
+            double2 o;
+            o.x = sing ? __builtin_nan("") : 2.0 * kroot[c].re;
+            o.y = sing ? __builtin_nan("") : 2.0 * kroot[c].im;
+            static_cast<double2*>(a.cur)[(int64_t)c * a.ld + q] = o;
+          }
+        }
       } else {
-        o.x = -2.0 * res.re;
-        o.y = -2.0 * res.im;
+        double2 o;
+        if (sing) {
+          o.x = __builtin_nan("");
+          o.y = __builtin_nan("");
+        } else {
+          o.x = -2.0 * res.re;
+          o.y = -2.0 * res.im;
+        }
+        static_cast<double2*>(a.out)[q] = o;
       }
-      static_cast<double2*>(a.out)[q] = o;
       if (a.status) a.status[q] = sing ? PT_SINGULAR : PT_OK;
     }
   }

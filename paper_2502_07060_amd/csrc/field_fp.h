@@ -42,6 +42,8 @@ struct FpConst {
   int32_t r4;     // R^4 mod p, balanced   (output fix-up factor)
   int32_t r4s;    // R^4 2^-32 mod p, balanced (output fix-up of the register kernel, whose
                   // accumulators carry the extra 2^32 of lazily reduced scalars)
+  int32_t r3;     // R^3 mod p, balanced   (fix-up of a root current, degree n - 1 in eps)
+  int32_t r3s;    // R^3 2^-32 mod p, balanced (the same in the register kernel)
   int32_t two;    // 2 R mod p, balanced   (the constant 2, Montgomery form)
   int32_t two32;  // 2^33 mod p, balanced  (2 R 2^-32: the constant 2 with an extra 2^-32)
   int32_t inv2;   // 2^-1 R mod p, balanced (the constant 1/2, Montgomery form)

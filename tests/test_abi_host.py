@@ -211,3 +211,18 @@ def test_ffops_argument_checks():
     assert L.bg_fp_divide(P, 0, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
     assert L.bg_fp_divide_scalar(P, 4, D, ctypes.c_uint32(0), D, NULL, NULL) == bg.BG_EDOMAIN
     assert L.bg_fp_divide_scalar(P, 4, D, ctypes.c_uint32(2147483629), D, NULL, NULL) == bg.BG_EINVAL
+
+
+def test_currents_and_state_sum_argument_checks():
+    L = bg.lib()
+    D = ctypes.c_void_p(0x1000)
+    P = ctypes.c_uint32(2147483629)
+    assert L.bg_currents_fp(15, 4, 10, 10, P, D, D, D, NULL, NULL) == bg.BG_EDOMAIN
+    assert L.bg_currents_fp(5, 4, 10, 10, ctypes.c_uint32(2147483631), D, D, D, NULL, NULL) == bg.BG_ENOTPRIME
+    assert L.bg_currents_fp(5, 4, 10, 10, P, D, D, NULL, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_currents_c128(5, 4, 10, 5, D, D, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_currents_c128(5, 4, 0, 0, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
+    assert L.bg_state_sum_fp(3, 10, 10, P, D, D, D, D, D, NULL, NULL) == bg.BG_EDOMAIN
+    assert L.bg_state_sum_fp(6, 10, 10, ctypes.c_uint32(2147483631), D, D, D, D, D, NULL, NULL) == bg.BG_ENOTPRIME
+    assert L.bg_state_sum_c128(6, 10, 10, D, D, NULL, D, D, NULL, NULL) == bg.BG_EINVAL
+    assert L.bg_state_sum_c128(6, 0, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
