@@ -759,19 +759,30 @@ def main(argv=None):
             "variant": fp_run["variant"],
         },
     }
+    def progress(what):
+        print(f"[bench] {what} done", file=sys.stderr, flush=True)
+
+    progress("n = 8 workloads")
     line["alternating_metric"] = {
         "workload": "the two n = 8 workloads through bg_amplitudes_*_metric, metric diag(1,-1,1,-1,...)",
         "c8_d4": run_alternating("c8_d4", a.steps, a.warmup, main_run["kernel_ms"]),
         "fp8_d6": run_alternating("fp8_d6", a.steps, a.warmup, fp_run["kernel_ms"]),
     }
+    progress("alternating metric")
     line["states"] = run_states(a.steps, a.warmup)
+    progress("states")
     line["rational"] = run_rational(a.steps, a.warmup)
+    progress("rational")
     line["ffops"] = run_ffops(a.steps, a.warmup)
+    progress("ffops")
     line["cut"] = run_cut(a.steps, a.warmup)
+    progress("cut")
     if not a.no_batched:
         line["batched"] = run_batched(a.steps, a.warmup)
+        progress("batched")
     if not a.no_served:
         line["served"] = run_served(a.serve_requests)
+        progress("served")
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline("c8_d4", a.cpu_sample)
         line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 4)

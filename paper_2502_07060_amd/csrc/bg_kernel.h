@@ -92,8 +92,9 @@ struct Loader<FpField<DL, L>> {
     maxraw = maxraw > xi ? maxraw : xi;
     const uint32_t xc = xi < (uint32_t)a.fp.p ? xi : 0u;
     int32_t v = fp_from_canonical(xc, a.fp);
-    if constexpr (ALT) {
-      if (mu >= 2 && (mu & 1) == 0) v = fp_mul(v, a.ialt, a.fp);
+    if constexpr (ALT) {  // a select, so that the loads stay in one block
+      const int32_t w = fp_mul(v, a.ialt, a.fp);
+      v = (mu >= 2 && (mu & 1) == 0) ? w : v;
     }
     return v;
   }
@@ -112,11 +113,16 @@ struct Loader<C128Field<DL, L>> {
     const bool in = mu < a.d;
     const double2 v =
         static_cast<const double2*>(base)[((int64_t)l * a.d + (in ? mu : 0)) * a.ld + q];
-    if (!in) return cplx{0.0, 0.0};
+    // selects, not branches: an early return here lets the compiler sink each
+    // load into a block of its own, which serialises the point's loads
+    double re = in ? v.x : 0.0, im = in ? v.y : 0.0;
     if constexpr (ALT) {
-      if (mu >= 2 && (mu & 1) == 0) return cplx{-v.y, v.x};  // times i, exactly
+      const bool rot = mu >= 2 && (mu & 1) == 0;  // times i, exactly
+      const double r2 = rot ? -im : re, i2 = rot ? re : im;
+      re = r2;
+      im = i2;
     }
-    return cplx{v.x, v.y};
+    return cplx{re, im};
   }
   __device__ static cplx get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                                 uint32_t& maxraw) {
