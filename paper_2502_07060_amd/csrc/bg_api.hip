@@ -385,7 +385,7 @@ int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {
       bg_variant_info& o = out[count];
       o.index = i;
       o.lanes = reg[i].L;
-      o.comps_per_lane = reg[i].DL;
+      o.comps_per_lane = reg[i].DL / reg[i].split;
       o.lds_tables = reg[i].lds_tables ? 1 : 0;
       o.generic = reg[i].generic ? 1 : 0;
       o.padded = reg[i].padded ? 1 : 0;

@@ -18,6 +18,7 @@ namespace bg {
 // ---------------------------------------------------------------------------
 template <int DL, int L>
 struct FpField {
+  static constexpr int kDL = DL, kL = L;
   using E = int32_t;  // one component
   using S = int32_t;  // a scalar
   using A = int64_t;  // accumulator of one component
@@ -175,6 +176,7 @@ __device__ __forceinline__ cplx cmad(cplx a, cplx b, cplx acc) {
 
 template <int DL, int L>
 struct C128Field {
+  static constexpr int kDL = DL, kL = L;
   using E = cplx;
   using S = cplx;
   using A = cplx;

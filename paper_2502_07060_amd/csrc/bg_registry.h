@@ -27,6 +27,7 @@ struct Variant {
   const void* fn;
   unsigned (*lds_per_point)(int N) = nullptr;  // runtime-n kernels: LDS bytes per point
   bool padded = false;  // lane-group kernel whose table rows are padded to an odd number of 16-byte units
+  int split = 1;        // lane-group kernel: lanes per work item (DL / split components each)
 };
 
 std::vector<Variant>& registry();
@@ -91,12 +92,13 @@ unsigned wide_lds_bytes(int N) {
       &generic_lds_bytes<GenericLayout<FLD<DMAX_, 1>, DMAX_>>});                                \
   }
 
-// runtime-n kernel with G lanes sharing each point's tables (PAD: odd row stride)
-#define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_, PAD_)                                        \
-  namespace bg {                                                                                \
-  template __global__ void bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_, PAD_>(LaunchArgs, int);     \
-  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                           \
-      FIELDTAG, 0, DMAX_, G_, 0, true, true, 1,                                                 \
-      reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_, 1>, DMAX_, G_, PAD_>),           \
-      &wide_lds_bytes<WideLayout<FLD<DMAX_, 1>, DMAX_, G_, PAD_>>, PAD_});                     \
+// runtime-n kernel with G work items sharing each point's tables, LC lanes per
+// item (PAD: odd row stride)
+#define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_, PAD_, LC_)                                               \
+  namespace bg {                                                                                            \
+  template __global__ void bg_wide_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>(LaunchArgs, int);         \
+  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                                       \
+      FIELDTAG, 0, DMAX_, G_ * LC_, 0, true, true, 1,                                                       \
+      reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>),               \
+      &wide_lds_bytes<WideLayout<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>>, PAD_, LC_});                     \
   }

@@ -26,6 +26,11 @@
 // complex path.  F_p propagator inverses: each lane inverts its share of the
 // denominators with one batched inversion and one Fermat power.
 //
+// Component split (complex).  With Fld = C128Field<DL, LC>, LC > 1, each work
+// item belongs to LC adjacent lanes that hold DL = DMAX / LC components each
+// and sum dot products over DPP: LC times the lanes per point for the same
+// LDS footprint, which is what limits how many points a CU holds at large n.
+//
 // LDS access.  A lane reads whole table rows, with 16-byte reads (complex
 // elements are 16 bytes; F_p rows when they start on 16-byte boundaries).
 // The lanes of a wave read rows of unrelated ranges at once, so a row stride
@@ -51,6 +56,7 @@ struct WideLayout {
   // elements), so that rows start on every 16-byte bank group in turn and
   // F_p rows can be read with 16-byte loads
   static constexpr int kS = !PAD ? DMAX : (kFp ? 4 * (((DMAX + 3) / 4) | 1) : (DMAX | 1));
+  static_assert(Fld::kDL * Fld::kL >= DMAX && Fld::kDL * Fld::kL <= kS, "the lanes of an item cover a row");
   // F_p rows on 16-byte boundaries (the table bases are 16-byte aligned)
   static constexpr bool kVec4 = kFp && kS % 4 == 0;
   struct Off {
@@ -72,7 +78,7 @@ struct WideLayout {
     o.nDh = x;    x += up16((size_t)ncur(N) * sizeof(S));
     o.nc = x;     x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
     o.inv = x;    x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
-    o.part = x;   x += up16((size_t)G * kS * sizeof(A));
+    o.part = x;   x += up16((size_t)G * kS * sizeof(A));  // one row per item slot
     o.pscal = x;  x += up16((size_t)G * sizeof(S));
     o.flags = x;  x += 16;
     o.total = x;
@@ -96,8 +102,11 @@ struct WideRecursion {
   using A = typename Fld::A;
   using Lay = WideLayout<Fld, DMAX, G, PAD>;
   static constexpr int kS = Lay::kS;
-  using Rec = Recursion<Fld, 2, DMAX, 1>;  // scalar helpers
+  static constexpr int DL = Fld::kDL;   // components per lane
+  static constexpr int LC = Fld::kL;    // lanes per work item
+  using Rec = Recursion<Fld, 2, DL, LC>;  // scalar helpers
   static constexpr bool kFp = Fld::exact;
+  static_assert(!kFp || LC == 1, "the F_p lane-group kernel keeps whole vectors in one lane");
   static constexpr bool kPairs = G < 32;
 
   E* Jt;
@@ -109,9 +118,10 @@ struct WideRecursion {
   A* part;
   S* pscal;
   unsigned* flags;
-  int N, g;
+  int N, g, s, ln, co;  // item slot, component part, lane in the point, first component
 
-  __device__ WideRecursion(char* base, int N_, int g_) : N(N_), g(g_) {
+  __device__ WideRecursion(char* base, int N_, int ln_)
+      : N(N_), g(ln_ / LC), s(ln_ % LC), ln(ln_), co((ln_ % LC) * DL) {
     const auto o = Lay::offsets(N);
     Jt = reinterpret_cast<E*>(base + o.J);
     Mt = reinterpret_cast<E*>(base + o.mom);
@@ -130,11 +140,11 @@ struct WideRecursion {
   // one table row into registers with 16-byte LDS reads where the layout
   // allows (complex elements are 16 bytes; F_p rows of a padded layout start
   // on 16-byte boundaries)
-  __device__ __forceinline__ static void load_row(const E* row, E (&x)[DMAX]) {
+  __device__ __forceinline__ static void load_row(const E* row, E (&x)[DL]) {
     if constexpr (!kFp) {
       const double2* p = reinterpret_cast<const double2*>(row);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) {
+      for (int c = 0; c < DL; ++c) {
         const double2 v = p[c];
         x[c] = cplx{v.x, v.y};
       }
@@ -156,71 +166,72 @@ struct WideRecursion {
       if constexpr (DMAX % 2 == 1) x[DMAX - 1] = row[DMAX - 1];
     } else {
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) x[c] = row[c];
+      for (int c = 0; c < DL; ++c) x[c] = row[c];
     }
   }
-  __device__ __forceinline__ void loadJ(int r, E (&x)[DMAX]) const { load_row(Jt + r * kS, x); }
-  __device__ __forceinline__ void loadM(int l, E (&x)[DMAX]) const { load_row(Mt + l * kS, x); }
+  // this lane's components of a row
+  __device__ __forceinline__ void loadJ(int r, E (&x)[DL]) const { load_row(Jt + r * kS + co, x); }
+  __device__ __forceinline__ void loadM(int l, E (&x)[DL]) const { load_row(Mt + l * kS + co, x); }
   // primed P_S (F_p: reduced, from prefix sums; complex: left-to-right sum of k')
-  __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
+  __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DL]) const {
     if constexpr (kFp) {
-      E a[DMAX], b[DMAX];
+      E a[DL], b[DL];
       loadM(j + 1, a);
       loadM(i, b);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) P[c] = F.esub(a[c], b[c]);
+      for (int c = 0; c < DL; ++c) P[c] = F.esub(a[c], b[c]);
       P[0] = F.prime0(P[0]);
     } else {
       loadM(i, P);
       for (int l = i + 1; l <= j; ++l) {
-        E t[DMAX];
+        E t[DL];
         loadM(l, t);
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) P[c] = F.eadd(P[c], t[c]);
+        for (int c = 0; c < DL; ++c) P[c] = F.eadd(P[c], t[c]);
       }
     }
   }
   // F_p: primed P_S as unreduced differences Q_{j+1} - Q_i (|slot| <= 2h)
-  __device__ __forceinline__ void lazyP(const Fld& F, int i, int j, E (&P)[DMAX]) const {
-    E a[DMAX], b[DMAX];
+  __device__ __forceinline__ void lazyP(const Fld& F, int i, int j, E (&P)[DL]) const {
+    E a[DL], b[DL];
     loadM(j + 1, a);
     loadM(i, b);
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) P[c] = a[c] - b[c];
+    for (int c = 0; c < DL; ++c) P[c] = a[c] - b[c];
     P[0] = F.prime0(P[0]);
   }
   // complex: the primed momenta of both cuts c1 <= c2 of S = [i..j] in one
   // pass over the legs, each leg read once and added to the two sums it
   // belongs to, every sum still taken left to right:
   //   legs i..c1 -> A1, A2;  c1+1..c2 -> B1, A2;  c2+1..j -> B1, B2
-  __device__ __forceinline__ void pair_momenta(int i, int j, int c1, int c2, E (&A1)[DMAX], E (&B1)[DMAX],
-                                               E (&A2)[DMAX], E (&B2)[DMAX]) const {
+  __device__ __forceinline__ void pair_momenta(int i, int j, int c1, int c2, E (&A1)[DL], E (&B1)[DL],
+                                               E (&A2)[DL], E (&B2)[DL]) const {
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) A1[c] = B1[c] = A2[c] = B2[c] = cplx{0.0, 0.0};
+    for (int c = 0; c < DL; ++c) A1[c] = B1[c] = A2[c] = B2[c] = cplx{0.0, 0.0};
     int l = i;
     for (; l <= c1; ++l) {
-      E t[DMAX];
+      E t[DL];
       loadM(l, t);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) {
+      for (int c = 0; c < DL; ++c) {
         A1[c] = cadd(A1[c], t[c]);
         A2[c] = cadd(A2[c], t[c]);
       }
     }
     for (; l <= c2; ++l) {
-      E t[DMAX];
+      E t[DL];
       loadM(l, t);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) {
+      for (int c = 0; c < DL; ++c) {
         B1[c] = cadd(B1[c], t[c]);
         A2[c] = cadd(A2[c], t[c]);
       }
     }
     for (; l <= j; ++l) {
-      E t[DMAX];
+      E t[DL];
       loadM(l, t);
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) {
+      for (int c = 0; c < DL; ++c) {
         B1[c] = cadd(B1[c], t[c]);
         B2[c] = cadd(B2[c], t[c]);
       }
@@ -230,7 +241,7 @@ struct WideRecursion {
   // ---- loads: eps into the table, momenta, eps_n; F_p prefix sums --------
   __device__ void load(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad) {
     const int rows = (2 * N + 1) * DMAX;  // eps_0..eps_N, k_0..k_{N-1}
-    for (int r = g; r < rows; r += G) {
+    for (int r = ln; r < rows; r += G * LC) {
       const int which = r / DMAX, c = r % DMAX;
       if (which <= N) {
         const E e = Loader<Fld>::get_rt(a, a.pols, which, c, q, bad);
@@ -247,7 +258,7 @@ struct WideRecursion {
         }
       }
     }
-    if (g == 0) *flags = 0u;
+    if (ln == 0) *flags = 0u;
     group_sync();
     if constexpr (kFp) {
       if (g < DMAX) {  // prefix sums, one component per lane
@@ -260,7 +271,7 @@ struct WideRecursion {
       }
       group_sync();
       for (int l = g; l < N; l += G) {  // nc(l) = P_l . eps_l
-        E Pp[DMAX], e[DMAX];
+        E Pp[DL], e[DL];
         lazyP(F, l, l, Pp);
         loadJ(rid(l, l), e);
         nct[rid(l, l)] = F.template ndot<4>(Pp, e);
@@ -279,10 +290,10 @@ struct WideRecursion {
         int len = 2, base = 0;
         while (r >= base + (N - len + 1)) { base += N - len + 1; ++len; }
         const int i = r - base;
-        E Pp[DMAX], Pu[DMAX];
+        E Pp[DL], Pu[DL];
         primedP(F, i, i + len - 1, Pp);
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+        for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
         Pu[0] = F.prime0(Pp[0]);
         int32_t y = F.ndot(Pp, Pu);
         if (y == 0) { singular = true; y = F.k.one; }
@@ -312,15 +323,15 @@ struct WideRecursion {
   // as an int64 sum of products; complex: PA, PB are the primed P_A, P_B
   // (Pp unused), nDs sums -(J_A.J_B).
   template <class NDS>
-  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DMAX], const E (&PA)[DMAX],
-                      const E (&PB)[DMAX], A (&K)[DMAX], NDS& nDs) const {
-    E JA[DMAX], JB[DMAX];
+  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DL], const E (&PA)[DL],
+                      const E (&PB)[DL], A (&K)[DL], NDS& nDs) const {
+    E JA[DL], JB[DL];
     const int ra = rid(i, c), rb = rid(c + 1, j);
     loadJ(ra, JA);
     loadJ(rb, JB);
     const S nDm = F.ndot_u(JA, JB);  // -(J_A . J_B)
     if constexpr (kFp) {
-      E Qt[DMAX];
+      E Qt[DL];
       loadM(c + 1, Qt);
       const S nc2 = F.template ndot_sub<4>(Pp, JA, nct[ra]);   // -(P_B . J_A)
       const S nc3 = F.template ndot_sub<4>(Pp, JB, nct[rb]);   // -(P_A . J_B)
@@ -330,11 +341,11 @@ struct WideRecursion {
       F.fold(K);
       nDs = mad64(nDm, F.k.inv2, nDs);  // at most two terms per item
     } else {
-      E v[DMAX];
+      E v[DL];
       const S n2 = F.ndot(PB, JA);
       const S n3 = F.ndot(PA, JB);
 #pragma unroll
-      for (int x = 0; x < DMAX; ++x) v[x] = F.esub(PA[x], PB[x]);
+      for (int x = 0; x < DL; ++x) v[x] = F.esub(PA[x], PB[x]);
       v[0] = F.prime0(v[0]);  // P_A - P_B
       F.axpy(K, cplx{-0.5 * nDm.re, -0.5 * nDm.im}, v);
       F.axpy(K, F.sneg(n2), JB);
@@ -354,7 +365,7 @@ struct WideRecursion {
     int cnt = 0;
 #pragma unroll 2
     for (int t = c + 1; t < j; ++t) {
-      E JM[DMAX], JC[DMAX];
+      E JM[DL], JC[DL];
       loadJ(rm, JM);
       loadJ(rc, JC);
       const S ne = F.ndot_u(JA, JC);
@@ -368,7 +379,7 @@ struct WideRecursion {
     F.fold(K);
   }
 
-  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result, E (&kroot)[DMAX]) {
+  __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result, E (&kroot)[DL]) {
     uint32_t bad = 0;
     bool singular = false;
     load(F, a, q, bad);
@@ -381,19 +392,19 @@ struct WideRecursion {
       const int items = nr * per;
       const bool own = g < nr;
       const int oi = g, oj = g + m - 1;         // the range this lane owns
-      A K[DMAX];
+      A K[DL];
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) K[c] = F.azero();
+      for (int c = 0; c < DL; ++c) K[c] = F.azero();
       S nDsum = F.szero();
       for (int k0 = 0; k0 < items; k0 += G) {
         const int k = k0 + g;
         if (k < items) {
           const int i = k / per, u = k % per, j = i + m - 1;
-          E Pp[DMAX];
+          E Pp[DL];
           if constexpr (kFp) lazyP(F, i, j, Pp);
-          A Kp[DMAX];
+          A Kp[DL];
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) Kp[c] = F.azero();
+          for (int c = 0; c < DL; ++c) Kp[c] = F.azero();
           const int c1 = i + u, c2 = kPairs ? j - 1 - u : c1;
           if constexpr (kFp) {
             int64_t nDs = 0;
@@ -403,20 +414,20 @@ struct WideRecursion {
           } else {
             S nDs = F.szero();
             if constexpr (kPairs) {
-              E PA1[DMAX], PB1[DMAX], PA2[DMAX], PB2[DMAX];
+              E PA1[DL], PB1[DL], PA2[DL], PB2[DL];
               pair_momenta(i, j, c1, c2, PA1, PB1, PA2, PB2);
               cut(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
               if (c2 != c1) cut(F, i, j, c2, Pp, PA2, PB2, Kp, nDs);
             } else {
-              E PA[DMAX], PB[DMAX];
+              E PA[DL], PB[DL];
               primedP(F, i, c1, PA);
               primedP(F, c1 + 1, j, PB);
               cut(F, i, j, c1, Pp, PA, PB, Kp, nDs);
             }
-            pscal[g] = nDs;
+            if (s == 0) pscal[g] = nDs;
           }
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) part[g * kS + c] = Kp[c];
+          for (int c = 0; c < DL; ++c) part[g * kS + co + c] = Kp[c];
         }
         group_sync();
         if (own) {
@@ -425,7 +436,7 @@ struct WideRecursion {
           for (int kk = lo; kk < hi; ++kk) {
             const int slot = kk - k0;
 #pragma unroll
-            for (int c = 0; c < DMAX; ++c) K[c] = add_acc(F, K[c], part[slot * kS + c]);
+            for (int c = 0; c < DL; ++c) K[c] = add_acc(F, K[c], part[slot * kS + co + c]);
             nDsum = Rec::accumulate_scalar(F, nDsum, pscal[slot]);
           }
         }
@@ -434,14 +445,14 @@ struct WideRecursion {
       if (own) {
         const bool root = (m == N);
         S nDhS;
-        E Pp[DMAX];
+        E Pp[DL];
         if constexpr (kFp) {
           nDhS = nDsum;  // the items' sums already carry the factor 1/2
           lazyP(F, oi, oj, Pp);
           // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
-          E QQ[DMAX];
+          E QQ[DL];
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) QQ[c] = Mat(oi, c) + Mat(oj + 1, c);  // once per range
+          for (int c = 0; c < DL; ++c) QQ[c] = Mat(oi, co + c) + Mat(oj + 1, co + c);  // once per range
           F.axpy(K, nDhS, QQ);
           F.fold(K);
         } else {
@@ -451,38 +462,38 @@ struct WideRecursion {
         if (!root) {
           const int id = rid(oi, oj);
           nDht[id] = nDhS;
-          E Jn[DMAX];
+          E Jn[DL];
           if constexpr (kFp) {
             const S inv2 = invt[id];
 #pragma unroll
-            for (int c = 0; c < DMAX; ++c) {
+            for (int c = 0; c < DL; ++c) {
               Jn[c] = F.finish_mul32(K[c], inv2);
-              Jat(id, c) = Jn[c];
+              Jat(id, co + c) = Jn[c];
             }
             nct[id] = F.template ndot<4>(Pp, Jn);
           } else {
-            E Pu[DMAX];
+            E Pu[DL];
 #pragma unroll
-            for (int c = 0; c < DMAX; ++c) Pu[c] = Pp[c];
+            for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
             Pu[0] = F.prime0(Pp[0]);
             const S y = F.ndot(Pp, Pu);
             const S inv2 = Rec::c_inverse_times(y, -2.0, singular);
 #pragma unroll
-            for (int c = 0; c < DMAX; ++c) {
+            for (int c = 0; c < DL; ++c) {
               Jn[c] = F.mul(F.finish(K[c]), inv2);
-              Jat(id, c) = Jn[c];
+              Jat(id, co + c) = Jn[c];
             }
           }
         } else {
-          E Kf[DMAX], en[DMAX];
+          E Kf[DL], en[DL];
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) {
+          for (int c = 0; c < DL; ++c) {
             Kf[c] = F.finish(K[c]);
-            en[c] = En[c];
+            en[c] = En[co + c];
           }
           result = F.ndot_u(en, Kf);
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) kroot[c] = Kf[c];
+          for (int c = 0; c < DL; ++c) kroot[c] = Kf[c];
         }
       }
       group_sync();
@@ -501,31 +512,34 @@ struct WideRecursion {
   }
 };
 
-// G lanes per point (G divides 64), blockDim.x / G points per block, LDS from the host
-// (points per block x WideLayout::offsets(N).total bytes).
+// G items per point, each on LC = Fld::kL adjacent lanes (G LC divides 64),
+// blockDim.x / (G LC) points per block, LDS from the host (points per block x
+// WideLayout::offsets(N).total bytes).
 template <class Fld, int DMAX, int G, bool PAD>
 __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   extern __shared__ __align__(16) char lds[];
   using Lay = WideLayout<Fld, DMAX, G, PAD>;
-  static_assert(G >= 16 && 64 % G == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
-  const int g = (int)(threadIdx.x % G);
-  const int pb = (int)(threadIdx.x / G);
-  const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / G) + pb;
+  using WR = WideRecursion<Fld, DMAX, G, PAD>;
+  constexpr int GL = G * WR::LC;  // lanes per point
+  static_assert(G >= 16 && 64 % GL == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
+  const int t = (int)(threadIdx.x % GL);
+  const int pb = (int)(threadIdx.x / GL);
+  const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / GL) + pb;
   const bool valid = q0 < a.npts;
   const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
-  WideRecursion<Fld, DMAX, G, PAD> W(lds + (size_t)pb * Lay::offsets(N).total, N, g);
+  WR W(lds + (size_t)pb * Lay::offsets(N).total, N, t);
   typename Fld::S res;
-  typename Fld::E kroot[DMAX];
+  typename Fld::E kroot[WR::DL];
   if constexpr (Fld::exact) {
     Fld F(a.fp, 0);
     W.run(F, a, q, res, kroot);
-    if (valid && g == 0) {
+    if (valid && t == 0) {
       const unsigned fl = *W.flags;
       const uint8_t st = (fl & 1u) ? PT_BADRESIDUE : ((fl & 2u) ? PT_SINGULAR : PT_OK);
       if (a.cur) {
         // root current K = 2 K', kroot scaled by R^-3: one product with R^3
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
+        for (int c = 0; c < WR::DL; ++c) {
           if (c < a.d) {
             uint32_t v = 0xFFFFFFFFu;
             if (st == PT_OK) {
@@ -547,21 +561,23 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
       if (a.status) a.status[q] = st;
     }
   } else {
-    Fld F(0);
+    Fld F(W.s);
     W.run(F, a, q, res, kroot);
-    if (valid && g == 0) {
+    // the lanes of item slot 0 hold the root current, DL components each
+    if (valid && W.g == 0) {
       const bool sing = (*W.flags & 2u) != 0;
       if (a.cur) {
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
-          if (c < a.d) {
+        for (int c = 0; c < WR::DL; ++c) {
+          const int mu = W.co + c;
+          if (mu < a.d) {
             double2 o;
             o.x = sing ? __builtin_nan("") : 2.0 * kroot[c].re;
             o.y = sing ? __builtin_nan("") : 2.0 * kroot[c].im;
-            static_cast<double2*>(a.cur)[(int64_t)c * a.ld + q] = o;
+            static_cast<double2*>(a.cur)[(int64_t)mu * a.ld + q] = o;
           }
         }
-      } else {
+      } else if (W.s == 0) {
         double2 o;
         if (sing) {
           o.x = __builtin_nan("");
@@ -572,7 +588,7 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
         }
         static_cast<double2*>(a.out)[q] = o;
       }
-      if (a.status) a.status[q] = sing ? PT_SINGULAR : PT_OK;
+      if (a.status && W.s == 0) a.status[q] = sing ? PT_SINGULAR : PT_OK;
     }
   }
 }
