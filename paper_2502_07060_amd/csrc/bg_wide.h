@@ -57,8 +57,9 @@ struct WideLayout {
   // F_p rows can be read with 16-byte loads
   static constexpr int kS = !PAD ? DMAX : (kFp ? 4 * (((DMAX + 3) / 4) | 1) : (DMAX | 1));
   static_assert(Fld::kDL * Fld::kL >= DMAX && Fld::kDL * Fld::kL <= kS, "the lanes of an item cover a row");
-  // F_p rows on 16-byte boundaries (the table bases are 16-byte aligned)
-  static constexpr bool kVec4 = kFp && kS % 4 == 0;
+  // F_p rows, and each lane's part of a row, on 16-byte boundaries (the
+  // table bases are 16-byte aligned)
+  static constexpr bool kVec4 = kFp && kS % 4 == 0 && Fld::kDL % 4 == 0;
   struct Off {
     unsigned J, mom, epsn, nDh, nc, inv, part, pscal, flags, total;
   };
@@ -106,7 +107,6 @@ struct WideRecursion {
   static constexpr int LC = Fld::kL;    // lanes per work item
   using Rec = Recursion<Fld, 2, DL, LC>;  // scalar helpers
   static constexpr bool kFp = Fld::exact;
-  static_assert(!kFp || LC == 1, "the F_p lane-group kernel keeps whole vectors in one lane");
   static constexpr bool kPairs = G < 32;
 
   E* Jt;
@@ -151,19 +151,13 @@ struct WideRecursion {
     } else if constexpr (Lay::kVec4) {
       const int4* p4 = reinterpret_cast<const int4*>(row);
 #pragma unroll
-      for (int q = 0; q < DMAX / 4; ++q) {
+      for (int q = 0; q < DL / 4; ++q) {
         const int4 v = p4[q];
         x[4 * q] = v.x;
         x[4 * q + 1] = v.y;
         x[4 * q + 2] = v.z;
         x[4 * q + 3] = v.w;
       }
-      if constexpr (DMAX % 4 >= 2) {
-        const int2 v = reinterpret_cast<const int2*>(row)[DMAX / 4 * 2];
-        x[DMAX / 4 * 4] = v.x;
-        x[DMAX / 4 * 4 + 1] = v.y;
-      }
-      if constexpr (DMAX % 2 == 1) x[DMAX - 1] = row[DMAX - 1];
     } else {
 #pragma unroll
       for (int c = 0; c < DL; ++c) x[c] = row[c];
@@ -531,25 +525,27 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   typename Fld::S res;
   typename Fld::E kroot[WR::DL];
   if constexpr (Fld::exact) {
-    Fld F(a.fp, 0);
+    Fld F(a.fp, W.s);
     W.run(F, a, q, res, kroot);
-    if (valid && t == 0) {
+    // the lanes of item slot 0 hold the root, DL components each
+    if (valid && W.g == 0) {
       const unsigned fl = *W.flags;
       const uint8_t st = (fl & 1u) ? PT_BADRESIDUE : ((fl & 2u) ? PT_SINGULAR : PT_OK);
       if (a.cur) {
         // root current K = 2 K', kroot scaled by R^-3: one product with R^3
 #pragma unroll
         for (int c = 0; c < WR::DL; ++c) {
-          if (c < a.d) {
+          const int mu = W.co + c;
+          if (mu < a.d) {
             uint32_t v = 0xFFFFFFFFu;
             if (st == PT_OK) {
               const int32_t m = fp_mul(kroot[c], a.fp.r3, a.fp);
               v = fp_to_canonical(fp_add(m, m, a.fp), a.fp);
             }
-            static_cast<uint32_t*>(a.cur)[(int64_t)c * a.ld + q] = v;
+            static_cast<uint32_t*>(a.cur)[(int64_t)mu * a.ld + q] = v;
           }
         }
-      } else {
+      } else if (W.s == 0) {
         uint32_t outv = 0xFFFFFFFFu;
         if (st == PT_OK) {
           int32_t m = fp_mul(res, a.fp.r4, a.fp);
@@ -558,7 +554,7 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
         }
         static_cast<uint32_t*>(a.out)[q] = outv;
       }
-      if (a.status) a.status[q] = st;
+      if (a.status && W.s == 0) a.status[q] = st;
     }
   } else {
     Fld F(W.s);
