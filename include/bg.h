@@ -415,6 +415,7 @@ typedef struct {
                            lanes share one point's tables)                       */
   int padded;           /* lanes > 1 runtime-n kernel whose LDS table rows are
                            padded to an odd number of 16-byte units            */
+  int max_d;            /* largest d the kernel handles                        */
   int selected;         /* 1 if this variant is the one currently in use        */
 } bg_variant_info;
 

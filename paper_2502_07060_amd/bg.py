@@ -131,7 +131,7 @@ def bg_version() -> int:
 class bg_variant_info(ctypes.Structure):
     _fields_ = [("index", ctypes.c_int), ("lanes", ctypes.c_int), ("comps_per_lane", ctypes.c_int),
                 ("lds_tables", ctypes.c_int), ("generic", ctypes.c_int), ("padded", ctypes.c_int),
-                ("selected", ctypes.c_int)]
+                ("max_d", ctypes.c_int), ("selected", ctypes.c_int)]
 
 
 def bg_variants(field: int, n: int, d: int):

@@ -389,6 +389,7 @@ int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {
       o.lds_tables = reg[i].lds_tables ? 1 : 0;
       o.generic = reg[i].generic ? 1 : 0;
       o.padded = reg[i].padded ? 1 : 0;
+      o.max_d = reg[i].generic ? reg[i].DL : reg[i].DL * reg[i].L;
       o.selected = (&reg[i] == cur) ? 1 : 0;
     }
     ++count;

@@ -119,23 +119,23 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
 }
 
 // Selections as text, one line per pinned (field, n, d):
-//   field n d lanes comps_per_lane lds_tables generic padded
+//   field n d lanes comps_per_lane lds_tables generic padded max_d
 // Lines name kernels by their shape, so a file stays valid across builds that
 // register kernels in another order; lines with no matching kernel are skipped.
 extern "C" int bg_tune_save(const char* path) {
   if (!path) return BG_EINVAL;
   FILE* f = fopen(path, "w");
   if (!f) return BG_EINVAL;
-  fprintf(f, "# field n d lanes comps_per_lane lds_tables generic padded\n");
-  bg_variant_info vs[64];
+  fprintf(f, "# field n d lanes comps_per_lane lds_tables generic padded max_d\n");
+  bg_variant_info vs[128];
   for (int field = 0; field <= 1; ++field)
     for (int n = 3; n <= BG_MAX_N; ++n)
       for (int d = 1; d <= BG_MAX_D; ++d) {
-        const int c = std::min(64, bg_variants(field, n, d, vs, 64));
+        const int c = std::min(128, bg_variants(field, n, d, vs, 128));
         for (int k = 0; k < c; ++k)
           if (vs[k].selected && bg::is_pinned(field, n, d))
-            fprintf(f, "%d %d %d %d %d %d %d %d\n", field, n, d, vs[k].lanes, vs[k].comps_per_lane,
-                    vs[k].lds_tables, vs[k].generic, vs[k].padded);
+            fprintf(f, "%d %d %d %d %d %d %d %d %d\n", field, n, d, vs[k].lanes, vs[k].comps_per_lane,
+                    vs[k].lds_tables, vs[k].generic, vs[k].padded, vs[k].max_d);
       }
   fclose(f);
   return BG_OK;
@@ -149,13 +149,14 @@ extern "C" int bg_tune_load(const char* path) {
   int applied = 0;
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int field, n, d, lanes, dl, lt, gen, pad = 0;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d", &field, &n, &d, &lanes, &dl, &lt, &gen, &pad) < 7) continue;
-    bg_variant_info vs[64];
-    const int c = bg_variants(field, n, d, vs, 64);
-    for (int k = 0; k < std::min(c, 64); ++k)
+    int field, n, d, lanes, dl, lt, gen, pad = 0, maxd = 0;
+    if (sscanf(line, "%d %d %d %d %d %d %d %d %d", &field, &n, &d, &lanes, &dl, &lt, &gen, &pad, &maxd) < 7)
+      continue;
+    bg_variant_info vs[128];
+    const int c = bg_variants(field, n, d, vs, 128);
+    for (int k = 0; k < std::min(c, 128); ++k)
       if (vs[k].lanes == lanes && vs[k].comps_per_lane == dl && vs[k].lds_tables == lt && vs[k].generic == gen &&
-          vs[k].padded == pad) {
+          vs[k].padded == pad && (maxd == 0 || vs[k].max_d == maxd)) {
         if (bg_select_variant(field, n, d, vs[k].index) == BG_OK) ++applied;
         break;
       }

@@ -226,3 +226,28 @@ def test_currents_and_state_sum_argument_checks():
     assert L.bg_state_sum_fp(6, 10, 10, ctypes.c_uint32(2147483631), D, D, D, D, D, NULL, NULL) == bg.BG_ENOTPRIME
     assert L.bg_state_sum_c128(6, 10, 10, D, D, NULL, D, D, NULL, NULL) == bg.BG_EINVAL
     assert L.bg_state_sum_c128(6, 0, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == bg.BG_OK
+
+
+def test_tune_save_and_load_roundtrip(tmp_path):
+    """Pins written by bg_tune_save come back with bg_tune_load, including
+    the lane-group variants that differ only in padding or in lanes per item."""
+    picks = {}
+    for field, n, d in ((bg.BG_FIELD_C128, 14, 6), (bg.BG_FIELD_C128, 13, 6), (bg.BG_FIELD_FP, 12, 8),
+                        (bg.BG_FIELD_FP, 8, 6)):
+        vs = bg.bg_variants(field, n, d)
+        # prefer a padded or split lane-group variant when there is one
+        pick = next((v for v in vs if v["generic"] and (v["padded"] or v["comps_per_lane"] < 6)), vs[-1])
+        bg.bg_select_variant(field, n, d, pick["index"])
+        picks[(field, n, d)] = pick["index"]
+    path = str(tmp_path / "tune.txt")
+    try:
+        bg.bg_tune_save(path)
+        for (field, n, d) in picks:
+            bg.bg_select_variant(field, n, d, -1)
+        assert bg.bg_tune_load(path) >= len(picks)
+        for (field, n, d), idx in picks.items():
+            sel = [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]]
+            assert sel == [idx], (field, n, d)
+    finally:
+        for (field, n, d) in picks:
+            bg.bg_select_variant(field, n, d, -1)
