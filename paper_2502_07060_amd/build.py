@@ -48,9 +48,13 @@ for N in range(2, 8):
         REGISTER_VARIANTS.append(("c128", N, DL, L, LT, 1))
     if N <= 4:
         REGISTER_VARIANTS.append(("c128", N, 4, 1, True, 1))
-# F_p at n = 9: two lanes per point, the table of 35 currents in registers
-for DL in (3, 4, 5):
-    REGISTER_VARIANTS.append(("fp", 8, DL, 2, True, 1))
+# F_p at n = 9 and 10: two lanes per point, the table of 35 or 44 currents in
+# registers; complex at n = 9 with one component per lane on four lanes, or
+# two on two
+for N in (8, 9):
+    for DL in (3, 4, 5):
+        REGISTER_VARIANTS.append(("fp", N, DL, 2, True, 1))
+REGISTER_VARIANTS += [("c128", 8, 1, 4, True, 1), ("c128", 8, 2, 2, True, 1)]
 # Runtime-n kernels with LDS tables: (field, DMAX), one point per lane
 GENERIC_VARIANTS = [(f, dm) for f in ("fp", "c128") for dm in (4, 6, 8, 10)]
 # Runtime-n kernels with G lanes sharing each point's tables: (field, DMAX, G,
@@ -114,7 +118,7 @@ def generated_units():
 
 
 def unit_flags(src):
-    """Extra flags per translation unit.  The n = 8 and 9 register-resident
+    """Extra flags per translation unit.  The n ≥ 8 register-resident
     recursion kernels hold so much of the register file that a few more
     registers cost no occupancy, so they are scheduled for instruction-level
     parallelism rather than occupancy (measured on gfx950: complex n = 8 about
@@ -122,7 +126,7 @@ def unit_flags(src):
     smaller n the same strategy costs F_p kernels a wave per SIMD, so they
     keep the default."""
     name = os.path.basename(src)
-    if name.startswith("inst_") and ("_n8_" in name or "_n9_" in name):
+    if name.startswith("inst_") and any(f"_n{n}_" in name for n in (8, 9, 10)):
         return ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
     return []
 
@@ -174,7 +178,7 @@ def build(incremental: bool = False, jobs: int | None = None, verbose: bool = Fa
 
     jobs = jobs or min(8, os.cpu_count() or 4)
     # the biggest units first, so the long poles start early
-    sources.sort(key=lambda s: 0 if ("_n9_" in s or "_n8_" in s) else (1 if "_n7_" in s else 2))
+    sources.sort(key=lambda s: 0 if any(f"_n{n}_" in s for n in (8, 9, 10)) else (1 if "_n7_" in s else 2))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, sources))
     tmp = LIB + ".tmp"
