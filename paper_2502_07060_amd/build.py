@@ -48,13 +48,17 @@ for N in range(2, 8):
         REGISTER_VARIANTS.append(("c128", N, DL, L, LT, 1))
     if N <= 4:
         REGISTER_VARIANTS.append(("c128", N, 4, 1, True, 1))
-# F_p at n = 9 and 10: two lanes per point, the table of 35 or 44 currents in
-# registers; complex at n = 9 with one component per lane on four lanes, or
-# two on two
-for N in (8, 9):
+# n = 9 to 11 (35 to 54 currents per point): F_p on two lanes per point;
+# complex with one component per lane on four lanes or two on two (d <= 4),
+# and at n <= 10 two on four or three on two.  Some of these spill to scratch
+# and still beat the runtime-n kernels.
+for N in (8, 9, 10):
     for DL in (3, 4, 5):
         REGISTER_VARIANTS.append(("fp", N, DL, 2, True, 1))
-REGISTER_VARIANTS += [("c128", 8, 1, 4, True, 1), ("c128", 8, 2, 2, True, 1)]
+for N in (8, 9, 10):
+    REGISTER_VARIANTS += [("c128", N, 1, 4, True, 1), ("c128", N, 2, 2, True, 1)]
+for N in (8, 9):
+    REGISTER_VARIANTS += [("c128", N, 2, 4, True, 1), ("c128", N, 3, 2, True, 1)]
 # Runtime-n kernels with LDS tables: (field, DMAX), one point per lane
 GENERIC_VARIANTS = [(f, dm) for f in ("fp", "c128") for dm in (4, 6, 8, 10)]
 # Runtime-n kernels with G lanes sharing each point's tables: (field, DMAX, G,
@@ -126,7 +130,7 @@ def unit_flags(src):
     smaller n the same strategy costs F_p kernels a wave per SIMD, so they
     keep the default."""
     name = os.path.basename(src)
-    if name.startswith("inst_") and any(f"_n{n}_" in name for n in (8, 9, 10)):
+    if name.startswith("inst_") and any(f"_n{n}_" in name for n in (8, 9, 10, 11, 12)):
         return ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
     return []
 
@@ -178,7 +182,7 @@ def build(incremental: bool = False, jobs: int | None = None, verbose: bool = Fa
 
     jobs = jobs or min(8, os.cpu_count() or 4)
     # the biggest units first, so the long poles start early
-    sources.sort(key=lambda s: 0 if any(f"_n{n}_" in s for n in (8, 9, 10)) else (1 if "_n7_" in s else 2))
+    sources.sort(key=lambda s: 0 if any(f"_n{n}_" in s for n in (8, 9, 10, 11, 12)) else (1 if "_n7_" in s else 2))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, sources))
     tmp = LIB + ".tmp"
