@@ -313,11 +313,14 @@ struct WideRecursion {
   }
 
   // ---- one work item: contributions of cut c to K'(S), S = [i..j] ---------
+  // cut3: the three-gluon split [i..c] | [c+1..j] and the adjacent-pair terms
+  // of the four-gluon vertex that involve this cut; cut4 below adds the
+  // four-gluon splits of one or two cuts.
   // F_p: Pp holds P_S as unreduced differences, nDs accumulates -(J_A.J_B) / 2
   // as an int64 sum of products; complex: PA, PB are the primed P_A, P_B
   // (Pp unused), nDs sums -(J_A.J_B).
   template <class NDS>
-  __device__ void cut(const Fld& F, int i, int j, int c, const E (&Pp)[DL], const E (&PA)[DL],
+  __device__ void cut3(const Fld& F, int i, int j, int c, const E (&Pp)[DL], const E (&PA)[DL],
                       const E (&PB)[DL], A (&K)[DL], NDS& nDs) const {
     E JA[DL], JB[DL];
     const int ra = rid(i, c), rb = rid(c + 1, j);
@@ -350,15 +353,33 @@ struct WideRecursion {
     if (c >= i + 1) F.axpy(K, nDht[ra], JB);
     if (c <= j - 2) F.axpy(K, nDht[rb], JA);
     F.fold(K);
-    // four-gluon splits [i..c] | [c+1..t] | [t+1..j].  Range indices advance
-    // incrementally: with e = (right end - left end) of a range, extending
-    // [c+1..t] to [c+1..t+1] adds N - e, and shrinking [t+1..j] to [t+2..j]
-    // adds e - N (from the index formula of range_idx)
-    int rm = rid(c + 1, c + 1), lm = 0;
-    int rc = rid(c + 2, j), lc = j - c - 2;
+  }
+
+  // four-gluon splits [i..c] | [c+1..t] | [t+1..j] of cut c1 (j - c1 - 1 of
+  // them), then of cut c2 (j - c2 - 1; none when c2 == c1), in one loop: the
+  // two cuts of a pair item have m - 2 splits together, so every lane of a
+  // round runs the same number of iterations (two loops back to back would
+  // run m - 2 + m/2 - 1, with lanes masked off).  Range indices advance
+  // incrementally: with e = (right end - left end) of a range, extending
+  // [c+1..t] to [c+1..t+1] adds N - e, and shrinking [t+1..j] to [t+2..j]
+  // adds e - N (from the index formula of range_idx).
+  __device__ void cut4(const Fld& F, int i, int j, int c1, int c2, A (&K)[DL]) const {
+    E JA[DL];
+    loadJ(rid(i, c1), JA);
+    const int n1 = j - c1 - 1;
+    const int nt = n1 + (c2 != c1 ? j - c2 - 1 : 0);
+    int rm = rid(c1 + 1, c1 + 1), lm = 0;
+    int rc = rid(c1 + 2, j), lc = j - c1 - 2;
     int cnt = 0;
 #pragma unroll 2
-    for (int t = c + 1; t < j; ++t) {
+    for (int q = 0; q < nt; ++q) {
+      if (q == n1) {  // on to cut c2 (only reached when it has splits)
+        loadJ(rid(i, c2), JA);
+        rm = rid(c2 + 1, c2 + 1);
+        lm = 0;
+        rc = rid(c2 + 2, j);
+        lc = j - c2 - 2;
+      }
       E JM[DL], JC[DL];
       loadJ(rm, JM);
       loadJ(rc, JC);
@@ -402,22 +423,24 @@ struct WideRecursion {
           const int c1 = i + u, c2 = kPairs ? j - 1 - u : c1;
           if constexpr (kFp) {
             int64_t nDs = 0;
-            cut(F, i, j, c1, Pp, Pp, Pp, Kp, nDs);
-            if (kPairs && c2 != c1) cut(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
+            cut3(F, i, j, c1, Pp, Pp, Pp, Kp, nDs);
+            if (kPairs && c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
+            cut4(F, i, j, c1, c2, Kp);
             pscal[g] = fp_redc2(fp_fold(nDs, F.k), F.k);  // -(sum of J_A.J_B) / 2
           } else {
             S nDs = F.szero();
             if constexpr (kPairs) {
               E PA1[DL], PB1[DL], PA2[DL], PB2[DL];
               pair_momenta(i, j, c1, c2, PA1, PB1, PA2, PB2);
-              cut(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
-              if (c2 != c1) cut(F, i, j, c2, Pp, PA2, PB2, Kp, nDs);
+              cut3(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
+              if (c2 != c1) cut3(F, i, j, c2, Pp, PA2, PB2, Kp, nDs);
             } else {
               E PA[DL], PB[DL];
               primedP(F, i, c1, PA);
               primedP(F, c1 + 1, j, PB);
-              cut(F, i, j, c1, Pp, PA, PB, Kp, nDs);
+              cut3(F, i, j, c1, Pp, PA, PB, Kp, nDs);
             }
+            cut4(F, i, j, c1, c2, Kp);
             if (s == 0) pscal[g] = nDs;
           }
 #pragma unroll
