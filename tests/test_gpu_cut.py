@@ -37,7 +37,7 @@ def oracle_fp_currents(k, e, p=P):
     return out
 
 
-@pytest.mark.parametrize("n,d", [(3, 4), (4, 6), (6, 5), (8, 6), (8, 10), (9, 6), (12, 4), (14, 8)])
+@pytest.mark.parametrize("n,d", [(3, 4), (4, 6), (6, 5), (8, 6), (8, 10), (9, 6), (10, 6), (11, 8), (12, 4), (14, 8)])
 def test_currents_fp_every_variant(torch_dev, n, d):
     torch, _ = torch_dev
     m = 40 if n <= 8 else 10
@@ -70,7 +70,7 @@ def test_currents_fp_every_variant(torch_dev, n, d):
         bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1)
 
 
-@pytest.mark.parametrize("n,d", [(4, 4), (6, 6), (8, 4), (10, 6), (14, 10)])
+@pytest.mark.parametrize("n,d", [(4, 4), (6, 6), (8, 4), (9, 4), (10, 6), (11, 4), (14, 10)])
 def test_currents_c128_every_variant(torch_dev, n, d):
     torch, _ = torch_dev
     m = 30 if n <= 8 else 6

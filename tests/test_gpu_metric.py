@@ -35,7 +35,7 @@ def fp_inputs(n, d, m, seed):
     return k, e
 
 
-@pytest.mark.parametrize("n,d", [(3, 4), (4, 5), (5, 6), (6, 4), (8, 6), (8, 10), (9, 6), (12, 8), (14, 4)])
+@pytest.mark.parametrize("n,d", [(3, 4), (4, 5), (5, 6), (6, 4), (8, 6), (8, 10), (9, 6), (10, 8), (11, 6), (12, 8), (14, 4)])
 def test_fp_every_variant(torch_dev, n, d):
     k, e = fp_inputs(n, d, 60 if n <= 8 else 12, 50 + 10 * n + d)
     st_o, v_o = bgtest.oracle_fp(k, e, P, metric="alternating")
@@ -49,7 +49,7 @@ def test_fp_every_variant(torch_dev, n, d):
         bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1)
 
 
-@pytest.mark.parametrize("n,d", [(4, 4), (5, 6), (8, 4), (8, 7), (10, 6), (14, 10)])
+@pytest.mark.parametrize("n,d", [(4, 4), (5, 6), (8, 4), (8, 7), (9, 4), (10, 6), (11, 4), (14, 10)])
 def test_c128_every_variant(torch_dev, n, d):
     m = 60 if n <= 8 else 10
     rng = np.random.default_rng(900 + 10 * n + d)
