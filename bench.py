@@ -109,8 +109,21 @@ def cpu_baseline(kind: str, npts: int):
         bgtest.oracle_c(k, e)
     dt = time.perf_counter() - t0
     return {"value": npts / dt, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
+            "per_core": npts / dt / cores, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{npts} points of {kind} drawn with the same recipe and seed, pure-Python oracle, "
                       f"{cores} worker processes, {dt:.1f} s wall"}
+
+
+def _cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo (empty if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def run_workload(kind: str, steps: int, warmup: int):
