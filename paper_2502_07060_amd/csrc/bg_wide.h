@@ -195,23 +195,23 @@ struct WideRecursion {
     P[0] = F.prime0(P[0]);
   }
   // complex: the primed momenta of both cuts c1 <= c2 of S = [i..j] in one
-  // pass over the legs, each leg read once and added to the two sums it
-  // belongs to, every sum still taken left to right:
-  //   legs i..c1 -> A1, A2;  c1+1..c2 -> B1, A2;  c2+1..j -> B1, B2
+  // pass over the legs, each leg read once and added to the sums it belongs
+  // to, every sum still taken left to right:
+  //   legs i..c1 -> A1 (and A2, which starts as A1);  c1+1..c2 -> B1, A2;
+  //   c2+1..j -> B1, B2
   __device__ __forceinline__ void pair_momenta(int i, int j, int c1, int c2, E (&A1)[DL], E (&B1)[DL],
                                                E (&A2)[DL], E (&B2)[DL]) const {
 #pragma unroll
-    for (int c = 0; c < DL; ++c) A1[c] = B1[c] = A2[c] = B2[c] = cplx{0.0, 0.0};
+    for (int c = 0; c < DL; ++c) A1[c] = B1[c] = B2[c] = cplx{0.0, 0.0};
     int l = i;
     for (; l <= c1; ++l) {
       E t[DL];
       loadM(l, t);
 #pragma unroll
-      for (int c = 0; c < DL; ++c) {
-        A1[c] = cadd(A1[c], t[c]);
-        A2[c] = cadd(A2[c], t[c]);
-      }
+      for (int c = 0; c < DL; ++c) A1[c] = cadd(A1[c], t[c]);
     }
+#pragma unroll
+    for (int c = 0; c < DL; ++c) A2[c] = A1[c];
     for (; l <= c2; ++l) {
       E t[DL];
       loadM(l, t);
