@@ -48,9 +48,9 @@ for N in range(2, 8):
         REGISTER_VARIANTS.append(("c128", N, DL, L, LT, 1))
     if N <= 4:
         REGISTER_VARIANTS.append(("c128", N, 4, 1, True, 1))
-# n = 9 to 11 (35 to 54 currents per point): F_p on two lanes per point;
-# complex with one component per lane on four lanes or two on two (d <= 4),
-# and at n <= 10 two on four or three on two.  Some of these spill to scratch
+# n = 9 to 12 (35 to 65 currents per point): F_p on two lanes per point up
+# to n = 11; complex with one component per lane on four lanes (d <= 4, up to
+# n = 12) or two on two, and up to n = 11 two on four or three on two.  Some of these spill to scratch
 # and still beat the runtime-n kernels.
 for N in (8, 9, 10):
     for DL in (3, 4, 5):
@@ -59,6 +59,7 @@ for N in (8, 9, 10):
     REGISTER_VARIANTS += [("c128", N, 1, 4, True, 1), ("c128", N, 2, 2, True, 1)]
 for N in (8, 9):
     REGISTER_VARIANTS += [("c128", N, 2, 4, True, 1), ("c128", N, 3, 2, True, 1)]
+REGISTER_VARIANTS += [("c128", 10, 2, 4, True, 1), ("c128", 11, 1, 4, True, 1)]
 # Runtime-n kernels with LDS tables: (field, DMAX), one point per lane
 GENERIC_VARIANTS = [(f, dm) for f in ("fp", "c128") for dm in (4, 6, 8, 10)]
 # Runtime-n kernels with G lanes sharing each point's tables: (field, DMAX, G,

@@ -70,7 +70,7 @@ def test_currents_fp_every_variant(torch_dev, n, d):
         bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1)
 
 
-@pytest.mark.parametrize("n,d", [(4, 4), (6, 6), (8, 4), (9, 4), (10, 6), (11, 4), (14, 10)])
+@pytest.mark.parametrize("n,d", [(4, 4), (6, 6), (8, 4), (9, 4), (10, 6), (11, 4), (11, 7), (12, 4), (14, 10)])
 def test_currents_c128_every_variant(torch_dev, n, d):
     torch, _ = torch_dev
     m = 30 if n <= 8 else 6

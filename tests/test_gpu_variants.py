@@ -53,12 +53,12 @@ def test_every_c128_variant(torch_dev, n, d):
         bg.bg_select_variant(bg.BG_FIELD_C128, n, d, -1)
 
 
-@pytest.mark.parametrize("n", [9, 10, 11, 14])
+@pytest.mark.parametrize("n", [9, 10, 11, 12, 14])
 @pytest.mark.parametrize("d", [4, 6, 10])
 def test_every_runtime_n_variant_large_n(torch_dev, n, d):
     """Every variant at n ≥ 9, both fields: the runtime-n kernels (one point
     per lane, or a group of lanes per point) and the register-resident
-    kernels compiled for F_p at n = 9, 10 and complex at n = 9."""
+    kernels compiled for F_p at n = 9..11 and complex at n = 9..12."""
     m = 24 if n <= 11 else 10
     k, e = I.generic_fp(900 + 10 * n + d, n, d, m)
     rng = np.random.default_rng(n + 100 * d + 7)
