@@ -92,6 +92,26 @@ def test_primality_matches_oracle():
         assert (rc == bg.BG_OK) == is_prime(p), p
 
 
+def test_every_built_register_kernel_is_listed():
+    """Host-side: each register-resident instantiation in the build list shows
+    up in bg_variants for its (field, n) at some d <= 10, with its lanes,
+    components per lane and table placement, and no register kernel is listed
+    that the build does not compile."""
+    from paper_2502_07060_amd import build as B
+    want = {}
+    for field, N, DL, L, LT, W in B.REGISTER_VARIANTS:
+        f = bg.BG_FIELD_FP if field == "fp" else bg.BG_FIELD_C128
+        want.setdefault((f, N + 1), set()).add((L, DL, int(LT)))
+    for f in (bg.BG_FIELD_C128, bg.BG_FIELD_FP):
+        for n in range(3, 15):
+            got = set()
+            for d in range(1, 11):
+                for v in bg.bg_variants(f, n, d):
+                    if not v["generic"]:
+                        got.add((v["lanes"], v["comps_per_lane"], v["lds_tables"]))
+            assert got == want.get((f, n), set()), (f, n)
+
+
 def test_variant_listing_and_selection():
     """Host-side: every (field, n, d) has at least one variant, one is marked
     selected, pinning and unpinning work, and bad indices are rejected."""
