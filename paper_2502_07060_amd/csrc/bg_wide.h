@@ -400,6 +400,13 @@ struct WideRecursion {
     load(F, a, q, bad);
     inverses(F, singular);
     group_sync();
+    // complex: lane g owns [g..g+m-1] at every length m while g < N - m + 1,
+    // so it keeps that range's primed momentum as a running left-to-right sum
+    // (the same additions in the same order as summing the legs afresh)
+    [[maybe_unused]] E Pown[DL];
+    if constexpr (!kFp) {
+      if (g < N) loadM(g, Pown);
+    }
 
     for (int m = 2; m <= N; ++m) {
       const int nr = N - m + 1;                 // ranges of length m: i = 0 .. nr-1
@@ -474,7 +481,13 @@ struct WideRecursion {
           F.fold(K);
         } else {
           nDhS = Rec::half_scalar(F, nDsum);
-          primedP(F, oi, oj, Pp);
+          E t[DL];
+          loadM(oj, t);
+#pragma unroll
+          for (int c = 0; c < DL; ++c) {
+            Pown[c] = F.eadd(Pown[c], t[c]);
+            Pp[c] = Pown[c];
+          }
         }
         if (!root) {
           const int id = rid(oi, oj);
