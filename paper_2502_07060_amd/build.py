@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -103,8 +104,11 @@ def generated_units():
     units = {}
     for field, N, DL, L, LT, W in REGISTER_VARIANTS:
         tag, cls = FIELD[field]
-        # one unit per (field, n, lanes) keeps the units similar in size
-        units.setdefault(f"inst_{field}_n{N + 1}_l{L}", []).append(
+        # one unit per (field, n, lanes) keeps the units similar in size; from
+        # n = 9 on each kernel takes minutes to compile, so each gets its own
+        # unit and they compile in parallel
+        name = f"inst_{field}_n{N + 1}_l{L}" + (f"_dl{DL}" if N >= 8 else "")
+        units.setdefault(name, []).append(
             f"BG_REGISTER_RECURSION({tag}, {cls}, {N}, {DL}, {L}, {'true' if LT else 'false'}, {W})")
     for field, dm in GENERIC_VARIANTS:
         tag, cls = FIELD[field]
@@ -182,8 +186,11 @@ def build(incremental: bool = False, jobs: int | None = None, verbose: bool = Fa
         return obj
 
     jobs = jobs or min(8, os.cpu_count() or 4)
-    # the biggest units first, so the long poles start early
-    sources.sort(key=lambda s: 0 if any(f"_n{n}_" in s for n in (8, 9, 10, 11, 12)) else (1 if "_n7_" in s else 2))
+    # the biggest units (largest n) first, so the long poles start early
+    def size_rank(src):
+        m = re.search(r"inst_\w+?_n(\d+)_", os.path.basename(src))
+        return -int(m.group(1)) if m else 0
+    sources.sort(key=size_rank)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, sources))
     tmp = LIB + ".tmp"
