@@ -29,8 +29,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64
-INT_MAD_PEAK_TOPS = 39.3         # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one v_mad_u64_u32 per lane-cycle
+FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64 (published)
+LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9   # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12
+# Z_p roofline: the 32x32->64-bit integer multiply-add issue rate.  It has no
+# published figure; run_issue_rate measures it beside the FP64 FMA and the
+# peak is the published FP64 FMA rate scaled by the measured ratio of the two
+# (both measured at the same clock).  This constant is the nominal value (one
+# per lane slot per cycle at 2.4 GHz), used only where nothing was measured.
+INT_MAD_PEAK_TOPS = LANE_SLOTS_PER_S / 1e12
 
 
 def kernel_source_digest() -> str:
@@ -89,6 +95,47 @@ def time_launches(fn, steps: int, warmup: int):
     return total_ms, sum(per) / len(per), wall
 
 
+PROBE_NAMES = {0: "v_mad_i64_i32", 1: "v_mad_u64_u32", 2: "v_fma_f64", 3: "v_mul_lo_u32", 4: "v_mov_b32_dpp"}
+
+
+def run_issue_rate(blocks: int = 8192, iters: int = 2048, reps: int = 5):
+    """Issue rates of the recursion kernels' instruction classes on this
+    device (bg_issue_rate: 8 independent chains per lane, 2^21 lanes), the
+    derived Z_p peak, and the time of an almost empty launch."""
+    from paper_2502_07060_amd import bg
+    rates = {}
+    for kind, name in PROBE_NAMES.items():
+        r, ms = bg.bg_issue_rate(kind, blocks=blocks, iters=iters, reps=reps)
+        rates[name] = {"lane_ops_per_s": r, "ms_per_launch": ms, "per_lane_slot_cycle_at_2.4GHz": r / LANE_SLOTS_PER_S}
+    _, empty_ms = bg.bg_issue_rate(bg.BG_PROBE_MAD_I64_I32, blocks=1, iters=4, reps=50)
+    ratio = rates["v_mad_i64_i32"]["lane_ops_per_s"] / rates["v_fma_f64"]["lane_ops_per_s"]
+    return {
+        "method": f"{blocks} blocks x 256 lanes, 8 independent dependency chains per lane, {iters} rounds, "
+                  f"{reps} timed launches after one warm-up, HIP events on the launch stream",
+        "rates": rates,
+        "int_mad_over_fp64_fma": ratio,
+        "int_mad_peak_tops": ratio * FP64_PEAK_TFLOPS / 2,
+        "int_mad_peak_basis": "published FP64 FMA rate (78.6 TFLOP/s / 2 flops) x measured v_mad_i64_i32 / v_fma_f64",
+        "implied_clock_ghz": rates["v_fma_f64"]["lane_ops_per_s"] / (256 * 4 * 16) / 1e9,
+        "empty_launch_ms": empty_ms,
+    }
+
+
+def run_c5_small(steps: int, warmup: int, empty_launch_ms: float | None):
+    """Config c1: n = 5, d = 4, complex128, 10^4 points: HBM / launch bound."""
+    r = run_workload("c5_small", steps, warmup)
+    n, d, npts = r["n"], r["d"], r["npts"]
+    nbytes = npts * ((2 * n - 1) * d * 16 + 16 + 1)
+    achieved = nbytes / (r["kernel_ms"] * 1e-3) / 1e9
+    r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS * 1e3, "unit": "GB/s",
+                     "frac": achieved / (HBM_PEAK_TBS * 1e3), "traffic": None,
+                     "hbm_floor_ms": nbytes / (HBM_PEAK_TBS * 1e12) * 1e3}
+    r["empty_launch_ms"] = empty_launch_ms
+    r["workload"] = ("c5_small: n=5, d=4, complex128, 10^4 points, helicities (--+++), RAMBO sqrt(s)=1000, "
+                     "one launch per step")
+    return r
+
+
 def cpu_baseline(kind: str, npts: int):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import multiprocessing as mp
@@ -108,10 +155,35 @@ def cpu_baseline(kind: str, npts: int):
     else:
         bgtest.oracle_c(k, e)
     dt = time.perf_counter() - t0
+    one = cpu_single_core(kind, 4096 if kind != "c5_small" else 10_000)
     return {"value": npts / dt, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
-            "per_core": npts / dt / cores, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "all_cores_per_core": npts / dt / cores, "single_core": one,
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{npts} points of {kind} drawn with the same recipe and seed, pure-Python oracle, "
                       f"{cores} worker processes, {dt:.1f} s wall"}
+
+
+def cpu_single_core(kind: str, npts: int):
+    """The oracle in this process alone (one core) on the first npts points of
+    the same recipe and seed."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import bgtest
+    from paper_2502_07060_amd import inputs as I
+
+    w = I.config_workload(kind, npts=npts)
+    k, e = w["k"], w["eps"]
+    t0 = time.perf_counter()
+    if w["field"] == "fp":
+        for q in range(npts):
+            bgtest._fp_one((w["p"], k[q].astype(np.int64), e[q].astype(np.int64), bgtest.MM))
+    else:
+        for q in range(npts):
+            bgtest._c_one((k[q], e[q], bgtest.MM))
+    dt = time.perf_counter() - t0
+    return {"value": npts / dt, "unit": "amplitudes/s", "cores": 1,
+            "sample": f"first {npts} points of {kind} (same recipe and seed), one process, {dt:.1f} s"}
 
 
 def _cpu_model() -> str:
@@ -126,7 +198,7 @@ def _cpu_model() -> str:
     return ""
 
 
-def run_workload(kind: str, steps: int, warmup: int):
+def run_workload(kind: str, steps: int, warmup: int, int_peak_tops: float | None = None):
     import numpy as np
     import torch
 
@@ -158,9 +230,11 @@ def run_workload(kind: str, steps: int, warmup: int):
     bad = int((st != 0).sum().item())
     W = work_per_amplitude(n, d)
     if w["field"] == "fp":
+        peak = int_peak_tops or INT_MAD_PEAK_TOPS
         achieved = W * npts / (launch_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": INT_MAD_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / INT_MAD_PEAK_TOPS, "traffic": measured_traffic(kind)}
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(kind),
+                "peak_basis": "measured (issue_rate)" if int_peak_tops else "nominal: one per lane slot per cycle"}
     else:
         achieved = 8 * W * npts / (launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -569,6 +643,37 @@ def _serve_pool_inputs(key):
     return I.to_soa(k.astype(np.complex128)), I.to_soa(e.astype(np.complex128))
 
 
+def copy_bandwidth(mib: int = 512, reps: int = 5):
+    """Pinned host <-> device copy bandwidth (bytes/s), each direction alone
+    and both at once, timed with events on one stream per direction."""
+    import torch
+    n = mib << 20
+    h_src = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    h_dst = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    d_a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    d_b = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fns):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for st, f in fns:
+                with torch.cuda.stream(st):
+                    f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    h2d = lambda: d_a.copy_(h_src, non_blocking=True)
+    d2h = lambda: h_dst.copy_(d_b, non_blocking=True)
+    timed([(s1, h2d), (s2, d2h)])  # warm-up
+    t_in = timed([(s1, h2d)])
+    t_out = timed([(s2, d2h)])
+    t_both = timed([(s1, h2d), (s2, d2h)])
+    return {"h2d_bytes_per_s": n / t_in, "d2h_bytes_per_s": n / t_out, "bidirectional_bytes_per_s": 2 * n / t_both,
+            "method": f"{mib} MiB pinned <-> device, {reps} copies per direction, wall clock around the copies"}
+
+
 def run_served(count: int, fracs=(0.5, 0.7, 0.9), budget_gib: float = 8.0):
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
@@ -622,6 +727,15 @@ def run_served(count: int, fracs=(0.5, 0.7, 0.9), budget_gib: float = 8.0):
         f = bg.BG_FIELD_FP if field == "fp" else bg.BG_FIELD_C128
         bg.bg_autotune(f, n, d, p if field == "fp" else 0, npts=1 << 16, reps=3)
     mean_size = sum(r["npts"] for r in trace) / len(trace)
+    # host <-> device bytes of the whole trace: inputs in, results and statuses out
+    es_of = lambda r: 16 if r["field"] == "c128" else 4
+    bytes_in = sum(2 * r["n"] * r["d"] * es_of(r) * r["npts"] for r in trace)
+    bytes_out = sum((es_of(r) + 1) * r["npts"] for r in trace)
+    bw = copy_bandwidth()
+    # copies in and out run on separate DMA engines: the copy-bound span is the
+    # longer of the two directions (both directions at once measured too)
+    copy_bound_s = max(bytes_in / bw["h2d_bytes_per_s"], bytes_out / bw["d2h_bytes_per_s"],
+                       (bytes_in + bytes_out) / bw["bidirectional_bytes_per_s"])
     L = bg.lib()
     budget = int(budget_gib * (1 << 30))
 
@@ -658,7 +772,9 @@ def run_served(count: int, fracs=(0.5, 0.7, 0.9), budget_gib: float = 8.0):
         span = (done_max - t0) * 1e-9
         return {"throughput": sum(r["npts"] for r in trace) / span, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "launches": st["batches"],
-                "requests_sharing_a_launch": shared, "arena_peak_bytes": st["arena_peak"], "span_s": span}
+                "requests_sharing_a_launch": shared, "arena_peak_bytes": st["arena_peak"], "span_s": span,
+                "host_device_bytes_per_s": (bytes_in + bytes_out) / span,
+                "frac_of_copy_bound": copy_bound_s / span}
 
     replay(False, None)            # warm-up: first touches of pinned pages and kernels
     plain_sat = replay(True, None)
@@ -674,6 +790,8 @@ def run_served(count: int, fracs=(0.5, 0.7, 0.9), budget_gib: float = 8.0):
                     "d {4,6,10}, complex128 or Z_p, seed 5; inputs and outputs in pinned host memory, "
                     "latency from arrival to results on the host",
         "mean_request_points": mean_size, "arena_gib": budget_gib,
+        "copy_bound": {**bw, "trace_bytes_in": bytes_in, "trace_bytes_out": bytes_out,
+                       "copy_bound_span_s": copy_bound_s},
         "saturated": {"plain": plain_sat, "served": served_sat,
                       "served_over_plain": served_sat["throughput"] / plain_sat["throughput"]},
         "rates": rates, "nonzero_status": bad, "host_setup_s": t_gen,
@@ -702,7 +820,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 88-group workload")
     ap.add_argument("--no-served", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "batched", "served", "states", "rational", "ffops", "cut"],
+    ap.add_argument("--workload", choices=["both", "c8_d4", "fp8_d6", "c5_small", "issue_rate", "batched", "served",
+                                           "states", "rational", "ffops", "cut"],
                     default="both",
                     help="restrict to one workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -734,13 +853,21 @@ def main(argv=None):
     if a.workload == "cut":
         print(json.dumps(run_cut(a.steps, a.warmup)), flush=True)
         return
+    if a.workload == "issue_rate":
+        print(json.dumps(run_issue_rate()), flush=True)
+        return
+    if a.workload == "c5_small":
+        ir = run_issue_rate(iters=256)
+        print(json.dumps(run_c5_small(a.steps, a.warmup, ir["empty_launch_ms"])), flush=True)
+        return
     if a.workload != "both":
         r = run_workload(a.workload, a.steps, a.warmup)
         calibrate_copy(a.calibrate_copy)
         print(json.dumps({"workload": a.workload, **r}), flush=True)
         return
+    issue = run_issue_rate()
     main_run = run_workload("c8_d4", a.steps, a.warmup)
-    fp_run = run_workload("fp8_d6", a.steps, a.warmup)
+    fp_run = run_workload("fp8_d6", a.steps, a.warmup, int_peak_tops=issue["int_mad_peak_tops"])
     calibrate_copy(a.calibrate_copy)
     line = {
         "metric": "amplitudes/s at n=8 (C d=4, F_p d=6); served p50/p99 latency vs plain launch",
@@ -776,6 +903,9 @@ def main(argv=None):
         print(f"[bench] {what} done", file=sys.stderr, flush=True)
 
     progress("n = 8 workloads")
+    line["issue_rate"] = issue
+    line["c5_small"] = run_c5_small(a.steps, a.warmup, issue["empty_launch_ms"])
+    progress("c5_small")
     line["alternating_metric"] = {
         "workload": "the two n = 8 workloads through bg_amplitudes_*_metric, metric diag(1,-1,1,-1,...)",
         "c8_d4": run_alternating("c8_d4", a.steps, a.warmup, main_run["kernel_ms"]),
@@ -799,6 +929,7 @@ def main(argv=None):
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline("c8_d4", a.cpu_sample)
         line["fp8_d6"]["cpu_baseline"] = cpu_baseline("fp8_d6", a.cpu_sample // 4)
+        line["c5_small"]["cpu_baseline"] = {"single_core": cpu_single_core("c5_small", 10_000)}
     print(json.dumps(line), flush=True)
 
 

@@ -299,7 +299,11 @@ int bg_fp_divide_scalar(uint32_t p, int64_t count, const uint32_t* x, uint32_t y
                         uint32_t* z, uint8_t* status, void* hip_stream);
 
 /*
- * Batched form: many (field, n, d) groups in one call.  Each group has the
+ * Batched form: many (field, n, d) groups in one call.  The paper traces the
+ * fixed offset it sees at small event counts to run-time flexibility and
+ * proposes compiling ahead of time for a set number of legs and dimension
+ * (Sec. 3.2, discussion of Fig. 1b and Fig. 4); this call runs such
+ * precompiled kernels for many (n, d) at once.  Each group has the
  * layout and meaning of one bg_amplitudes_* call; every group is validated
  * before anything is enqueued (the first invalid group's error is returned).
  * Groups run the kernel variant selected for their (field, n, d), longest
@@ -332,8 +336,10 @@ int bg_batch_plan_launch(bg_batch_plan* plan, void* hip_stream);
 int bg_batch_plan_destroy(bg_batch_plan* plan);
 
 /*
- * Serving loop.  A server owns one device arena of hbm_budget_bytes (one
- * allocation at creation, on the current device), a few streams and one
+ * Serving loop.  The paper leaves memory management for a continuous stream
+ * of evaluations to future work (Sec. 3, the closing remarks on the
+ * implementation); this is one design for it.  A server owns one device
+ * arena of hbm_budget_bytes (one allocation at creation, on the current device), a few streams and one
  * scheduler thread.  Requests are bg_group records whose four pointers are
  * HOST memory (pinned memory lets copies overlap kernels): momenta and pols
  * [n][d][ld] with ld the host leading dimension, out [npts] and status
@@ -446,6 +452,29 @@ int bg_tune_save(const char* path);
 /* Applies selections written by bg_tune_save; returns how many matched a
  * compiled kernel, or a negative error code. */
 int bg_tune_load(const char* path);
+
+/*
+ * bg_issue_rate -- measures the issue rate of one VALU instruction class on
+ * the current device: blocks x 256 lanes each run 8 independent dependency
+ * chains of `iters` rounds of that instruction, reps timed launches after
+ * one warm-up on hip_stream.  *lane_ops_per_s receives lane-operations per
+ * second (every lane of a wave counts), *ms_per_launch (may be NULL) the
+ * time per launch.  This is the roofline denominator of the Z_p path, whose
+ * arithmetic is 64-bit integer multiply-add modulo p (Sec. 3) and has no
+ * published peak; BG_PROBE_FMA_F64 checks the method against the published
+ * FP64 rate.  Allocates and frees an 8-byte-per-lane sink buffer and
+ * synchronises the stream (a measurement call, not for hot paths).
+ * BG_EINVAL for an unknown kind or non-positive sizes.
+ */
+enum {
+  BG_PROBE_MAD_I64_I32 = 0,   /* v_mad_i64_i32: (int64) a * b + c, a, b int32 */
+  BG_PROBE_MAD_U64_U32 = 1,   /* v_mad_u64_u32                                */
+  BG_PROBE_FMA_F64 = 2,       /* v_fma_f64                                    */
+  BG_PROBE_MUL_LO_U32 = 3,    /* v_mul_lo_u32                                 */
+  BG_PROBE_DPP_MOV_B32 = 4    /* v_mov_b32 with a DPP lane permutation        */
+};
+int bg_issue_rate(int kind, int blocks, int iters, int reps, double* lane_ops_per_s,
+                  double* ms_per_launch, void* hip_stream);
 
 /* Human-readable text for a return code (static storage). */
 const char* bg_strerror(int code);

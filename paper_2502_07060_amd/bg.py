@@ -25,6 +25,8 @@ BG_PT_OK, BG_PT_SINGULAR, BG_PT_BADRESIDUE = 0, 1, 2
 BG_FIELD_C128, BG_FIELD_FP = 0, 1
 BG_METRIC_MOSTLY_MINUS, BG_METRIC_ALTERNATING = 0, 1
 BG_MAX_N, BG_MAX_D = 14, 10
+(BG_PROBE_MAD_I64_I32, BG_PROBE_MAD_U64_U32, BG_PROBE_FMA_F64, BG_PROBE_MUL_LO_U32,
+ BG_PROBE_DPP_MOV_B32) = range(5)
 FP_SENTINEL = 0xFFFFFFFF
 
 # every symbol include/bg.h declares, with its ctypes signature
@@ -88,6 +90,8 @@ _SIGNATURES = {
     "bg_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bg_server_now_ns": (ctypes.c_int64, []),
     "bg_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "bg_issue_rate": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "bg_version": (ctypes.c_int, []),
 }
@@ -160,6 +164,16 @@ def bg_autotune(field: int, n: int, d: int, p: int = 0, npts: int = 1 << 18, rep
     if rc < 0:
         raise BGError(rc, "bg_autotune")
     return rc, [(v, ms[i]) for i, v in enumerate(vs)]
+
+
+def bg_issue_rate(kind: int, blocks: int = 8192, iters: int = 2048, reps: int = 5, stream=None):
+    """(lane-operations per second, ms per launch) of one instruction class
+    (BG_PROBE_*) measured on the current device."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    rc = lib().bg_issue_rate(kind, blocks, iters, reps, ctypes.byref(rate), ctypes.byref(ms), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_issue_rate")
+    return rate.value, ms.value
 
 
 def bg_tune_save(path: str) -> None:

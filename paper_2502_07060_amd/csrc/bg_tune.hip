@@ -59,10 +59,12 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
   if (count <= 0) return count < 0 ? count : BG_ENOTIMPL;
   std::vector<bg_variant_info> vs(count);
   bg_variants(field, n, d, vs.data(), count);
-  // the current selection, restored if anything fails
+  // the current pin, restored if tuning fails (a pinned variant stays
+  // pinned; an unpinned (field, n, d) stays on its default)
   int prev = -1;
-  for (const auto& v : vs)
-    if (v.selected) prev = v.index;
+  if (bg::is_pinned(field, n, d))
+    for (const auto& v : vs)
+      if (v.selected) prev = v.index;
 
   const size_t elem = field == BG_FIELD_FP ? 4 : 16;
   const int64_t nelem = (int64_t)n * d * npts;
@@ -110,11 +112,10 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != BG_OK || best < 0) {
-    bg_select_variant(field, n, d, -1);
+    bg_select_variant(field, n, d, prev);
     return rc != BG_OK ? rc : BG_EHIP;
   }
   bg_select_variant(field, n, d, best);
-  (void)prev;
   return best;
 }
 

@@ -114,17 +114,33 @@ def natural_size(k, e):
     return np.prod(np.linalg.norm(e, axis=-1), axis=1) * scale ** (4 - n)
 
 
-def check_c(gpu, ref, k, e, rel=1e-11, label="", metric=MM):
+def check_c(gpu, ref, k, e, rel=1e-11, label="", metric=MM, vanishing=None, max_floor_frac=None):
     """Apply the tolerance rule; returns the number of points that needed the
-    rounding-error floor and the number that needed exact arbitration."""
+    rounding-error floor and the number that needed exact arbitration, and
+    prints both (they show in the test log with -s or on failure).
+
+    vanishing: optional mask of points whose amplitude is exactly zero (the
+    relative bar cannot hold there, so they always need the floor);
+    max_floor_frac: cap on the fraction of the other points that may pass
+    only through the floor or the arbitration."""
     err = np.abs(gpu - ref)
     bad = np.nonzero(~(err <= rel * np.abs(ref)))[0]
+    nvan = 0 if vanishing is None else int(np.count_nonzero(vanishing))
+    nb_reg = bad.size if vanishing is None else int(np.count_nonzero(~vanishing[bad]))
+    nreg = len(gpu) - nvan
+    print(f"[tolerance] {label}: {len(gpu)} points, {bad.size} outside the relative bar "
+          f"({nb_reg} of {nreg} non-vanishing)", flush=True)
+    if max_floor_frac is not None:
+        assert nb_reg <= max_floor_frac * max(nreg, 1), (
+            f"{label}: {nb_reg} of {nreg} non-vanishing points need the rounding floor "
+            f"(cap {max_floor_frac:.3f})")
     if bad.size == 0:
         return 0, 0
     ub = error_bound_c(k[bad], e[bad], metric)
     still = bad[~(err[bad] <= rel * np.abs(ref[bad]) + 2 * ub)]
     if still.size == 0:
         return bad.size, 0
+    print(f"[tolerance] {label}: {still.size} points arbitrated by exact evaluation", flush=True)
     assert still.size <= max(3, len(gpu) // 1000), (
         f"{label}: {still.size} of {len(gpu)} points outside tolerance, first {still[:5]}, "
         f"err {err[still[:5]]}, |ref| {np.abs(ref[still[:5]])}")

@@ -271,3 +271,24 @@ def test_tune_save_and_load_roundtrip(tmp_path):
     finally:
         for (field, n, d) in picks:
             bg.bg_select_variant(field, n, d, -1)
+
+
+def test_failed_autotune_keeps_the_previous_pin():
+    """A tuning call that fails (here: synthetic inputs too large to allocate,
+    or no GPU at all) leaves a pinned (field, n, d) on its pinned variant and
+    an unpinned one on its default."""
+    field, n, d = bg.BG_FIELD_FP, 8, 6
+    vs = bg.bg_variants(field, n, d)
+    default = [v["index"] for v in vs if v["selected"]]
+    pick = next(v for v in vs if not v["selected"])
+    try:
+        bg.bg_select_variant(field, n, d, pick["index"])
+        rc = bg.lib().bg_autotune(field, n, d, ctypes.c_uint32(2147483629), 1 << 40, 1, None, 0, None)
+        assert rc < 0
+        assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == [pick["index"]]
+        bg.bg_select_variant(field, n, d, -1)
+        rc = bg.lib().bg_autotune(field, n, d, ctypes.c_uint32(2147483629), 1 << 40, 1, None, 0, None)
+        assert rc < 0
+        assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == default
+    finally:
+        bg.bg_select_variant(field, n, d, -1)
