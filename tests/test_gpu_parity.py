@@ -111,7 +111,7 @@ def test_c128_helicity_points(torch_dev, n):
     assert np.array_equal(st_g, st_o)
     nminus = (hel < 0).sum(axis=1)
     van = (nminus <= 1) | (nminus >= n - 1)      # tree-level zeros in d = 4
-    bgtest.check_c(v_g, v_o, k, e, label=f"helicity n={n}", vanishing=van, max_floor_frac=0.02)
+    bgtest.check_c(v_g, v_o, k, e, label=f"helicity n={n}", vanishing=van, conditioned_only=True)
 
 
 # ----------------------------------------------------------------------------
@@ -134,7 +134,7 @@ def test_c5_small_full(torch_dev):
     st_g, v_g = gpu_c(torch_dev, k, e)
     st_o, v_o = bgtest.oracle_c(k, e)
     assert np.all(st_g == 0) and np.array_equal(st_g, st_o)
-    bgtest.check_c(v_g, v_o, k, e, label="c5_small", max_floor_frac=0.01)
+    bgtest.check_c(v_g, v_o, k, e, label="c5_small", conditioned_only=True)
     ratio = v_g / pt_mhv(k)
     assert np.max(np.abs(ratio - (-1) ** 5 * 4)) < 1e-9      # M / PT = (-1)^n 2^(n-3)
 
@@ -175,7 +175,7 @@ def test_c8_d4_full_size(torch_dev):
     nminus = (hel < 0).sum(axis=1)
     van = (nminus <= 1) | (nminus >= 7)
     bgtest.check_c(v_g[idx], v_o, k[idx], e[idx], label="c8_d4 sampled", vanishing=van[idx],
-                   max_floor_frac=0.02)
+                   conditioned_only=True)
     # Parke-Taylor on every MHV point with legs 1, 2 negative
     sel = (nminus == 2) & (hel[:, 0] < 0) & (hel[:, 1] < 0)
     r = v_g[sel] / pt_mhv(k[sel])
