@@ -108,8 +108,10 @@ def generated_units():
         # n = 9 on each kernel takes minutes to compile, so each gets its own
         # unit and they compile in parallel
         name = f"inst_{field}_n{N + 1}_l{L}" + (f"_dl{DL}" if N >= 8 else "")
+        lt = 'true' if LT else 'false'
         units.setdefault(name, []).append(
-            f"BG_REGISTER_RECURSION({tag}, {cls}, {N}, {DL}, {L}, {'true' if LT else 'false'}, {W})")
+            f"BG_REGISTER_RECURSION_FP({N}, {DL}, {L}, {lt}, {W})" if field == "fp" else
+            f"BG_REGISTER_RECURSION({tag}, {cls}, {N}, {DL}, {L}, {lt}, {W})")
     for field, dm in GENERIC_VARIANTS:
         tag, cls = FIELD[field]
         units.setdefault(f"inst_{field}_generic", []).append(

@@ -214,7 +214,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.metric = BG_METRIC_MOSTLY_MINUS;
   a.ialt = 0;
   a.cur = nullptr;
-  spec.fn = v->fn;
+  spec.fn = (field == FIELD_FP && v->fn_sc && fp_small_fold(fp)) ? v->fn_sc : v->fn;
   spec.generic = v->generic;
   spec.lanes = v->L;
   spec.N = n - 1;

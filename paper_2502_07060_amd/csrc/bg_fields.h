@@ -16,9 +16,34 @@ namespace bg {
 // ---------------------------------------------------------------------------
 // Z_p, signed balanced Montgomery (see field_fp.h)
 // ---------------------------------------------------------------------------
-template <int DL, int L>
+// Two reduction schedules, chosen per launch from the prime:
+//
+// * general (SC = false): any odd p < 2^31.  Accumulator bounds are tracked
+//   at compile time in half-units of 2^59 (an int64 holds 16); a fold leaves
+//   up to 2^61 + 2^32, so products are folded in small groups and the
+//   register kernel folds its current accumulators at fixed places.
+//
+// * small fold constant (SC = true): primes whose balanced 2^32 mod p is at
+//   most 2^22 in magnitude -- every prime 2^31 - c with c <= 2^21 (the
+//   largest primes below 2^31, the usual choice for modular evaluation), and
+//   every p < 2^22.  A fold then leaves |hi c32 + lo| <= 2^31 2^22 + 2^32 <
+//   2^54, so one fold empties an accumulator almost completely.  Bounds are
+//   tracked in units of 2^54 (an int64 holds 511):
+//     balanced x balanced             h^2 < 2^60             64
+//     unreduced difference x balanced 2h h < 2^61            128
+//     folded accumulator              < 2^54                 1
+//   and a lazily reduced scalar (one 32-bit REDC step of an input below
+//   2 units, 2^55) satisfies |s| <= h + 2^23, so
+//     lazy scalar x balanced          < 2^60 + 2^53          65
+//     lazy scalar x difference        < 2^61 + 2^54          129
+//     lazy scalar x c32 (lift of z)   < 2^53                 1
+//   The register kernel then folds a current's accumulator only when the
+//   next product would pass 511 units (every loop is unrolled, so the
+//   counters are compile-time constants).
+template <int DL, int L, bool SC = false>
 struct FpField {
   static constexpr int kDL = DL, kL = L;
+  static constexpr bool kSC = SC;
   using E = int32_t;  // one component
   using S = int32_t;  // a scalar
   using A = int64_t;  // accumulator of one component
@@ -39,47 +64,72 @@ struct FpField {
     else return time_lane ? -x : x;
   }
   __device__ __forceinline__ E esub(E a, E b) const { return fp_sub(a, b, k); }
+  // small fold constant only: |x| <= 2h (an int32 difference of balanced
+  // values) -> the same residue with |result| <= h + 2^23, by one product with
+  // 2^32 mod p (below 2^53) and one 32-bit REDC step (x c32 2^-32 = x mod p)
+  __device__ __forceinline__ E lazy_norm(int32_t x) const {
+    static_assert(SC, "needs |2^32 mod p| <= 2^22");
+    return fp_redc1(mul64(x, k.c32), k);
+  }
   __device__ __forceinline__ E eadd(E a, E b) const { return fp_add(a, b, k); }
   __device__ __forceinline__ S sneg(S a) const { return -a; }
   __device__ __forceinline__ S szero() const { return 0; }
   __device__ __forceinline__ A azero() const { return 0; }
 
-  // Accumulator bounds are tracked at compile time (every loop here is
-  // unrolled) in half-units of 2^59; an int64 holds 16.  A product of two
-  // balanced values (|v| <= h < 2^30) is below 2; with one factor an
-  // unreduced difference of two balanced values (< 2^31), below 4; with one
-  // factor a lazily reduced scalar (|s| < 1.5 2^30 + 1, from one 32-bit REDC
-  // step), below 3 (plus 2^30, negligible against the 2^59 kept spare); a
-  // folded accumulator is below 4.
-  static constexpr int kMaxU = 15;
+  // Bound bookkeeping.  General schedule: half-units of 2^59, an int64 holds
+  // 16 and 15 are used.  A product of two balanced values (|v| <= h < 2^30)
+  // is below 2; with one factor an unreduced difference of two balanced
+  // values (< 2^31), below 4; with one factor a lazily reduced scalar
+  // (|s| < 1.5 2^30 + 1, from one 32-bit REDC step), below 3 (plus 2^30,
+  // negligible against the 2^59 kept spare); a folded accumulator is below 4.
+  // Small-fold-constant schedule: units of 2^54 (table above).
+  static constexpr int kMaxU = SC ? 511 : 15;
+  static constexpr int kFoldU = SC ? 1 : 4;     // a folded accumulator
+  static constexpr int kLazyIn = SC ? 2 : 4;    // input limit of the lazy 32-bit REDC step
+  static constexpr int kRedc2In = SC ? 256 : 8;  // input limit of REDC2 (2^62)
+  // product classes, by the template tags the callers pass (UX = 2: balanced
+  // slots, UX = 4: unreduced differences; UZ = 2: balanced z lifted by R,
+  // UZ = 3: lazy z lifted by 2^32)
+  // Small fold constant: the currents themselves are lazily normalised
+  // (|J| <= h + 2^23, from two 32-bit REDC steps, see finish_mul32), so
+  // UX = 2 counts a product of two such values, (h + 2^23)^2 < 2^60 + 2^55
+  // (66 units), and UX = 4 an unreduced difference times one, 2h (h + 2^23)
+  // < 2^61 + 2^54 (129); UX = 5 (both operands lazily normalised) is 66 too.
+  static constexpr int ux_units(int UX) { return SC ? (UX == 4 ? 129 : 66) : UX; }
+  static constexpr int uz_units(int UZ) { return SC ? (UZ == 3 ? 1 : 64) : UZ; }
+  // products that enter a current's accumulator (SC schedule only; vectors
+  // are currents (|.| <= h + 2^23) or balanced prefix sums)
+  static constexpr int kPLazy = 66;       // lazy scalar x current
+  static constexpr int kPBal = 65;        // balanced scalar x current
+  static constexpr int kPBalDiff = 128;   // balanced scalar x unreduced sum of two balanced values
 
   template <int UX>
   __device__ __forceinline__ void acc_dot(A& t, int& u, const E* x, const E* y) const {
 #pragma unroll
     for (int c = 0; c < DL; ++c) {
-      if (u + UX > kMaxU) {
+      if (u + ux_units(UX) > kMaxU) {
         t = fp_fold(t, k);
-        u = 4;
+        u = kFoldU;
       }
       t = mad64(x[c], y[c], t);
-      u += UX;
+      u += ux_units(UX);
     }
   }
 
-  // group-wide sum of lane partials below u half-units each, then either a
-  // full REDC2 (input below 8, balanced result) or, LAZY, one 32-bit REDC
-  // step (input folded, result |s| < 1.5 2^30 + 1) for scalars that only
-  // multiply balanced vectors.  A lazy result is the REDC2 one times 2^32 mod
-  // p; a caller uses lazy scalars for every term of an accumulator, so the
-  // whole accumulator carries the same factor, removed once when it is
-  // finished.
+  // group-wide sum of lane partials below u each, then either a full REDC2
+  // (balanced result) or, LAZY, one 32-bit REDC step (general: input folded,
+  // result |s| < 1.5 2^30 + 1; small fold constant: input below 2^55, result
+  // |s| <= h + 2^23) for scalars that only multiply balanced vectors.  A lazy
+  // result is the REDC2 one times 2^32 mod p; a caller uses lazy scalars for
+  // every term of an accumulator, so the whole accumulator carries the same
+  // factor, removed once when it is finished.
   template <bool LAZY>
   __device__ __forceinline__ S finish_dot(A t, int u) const {
     if constexpr (L > 1) {
       if (L * u > kMaxU) {
         t = fp_fold(t, k);
-        u = 4;
-        if (L * u > kMaxU) {  // a second fold leaves below 2^59 + 2^33
+        u = kFoldU;
+        if (L * u > kMaxU) {  // general: a second fold leaves below 2^59 + 2^33
           t = fp_fold(t, k);
           u = 2;
         }
@@ -89,10 +139,10 @@ struct FpField {
       u *= L;
     }
     if constexpr (LAZY) {
-      if (u > 4) t = fp_fold(t, k);
+      if (u > kLazyIn) t = fp_fold(t, k);
       return fp_redc1(t, k);
     } else {
-      if (u > 7) t = fp_fold(t, k);
+      if (u >= kRedc2In) t = fp_fold(t, k);
       return fp_redc2(t, k);
     }
   }
@@ -126,12 +176,12 @@ struct FpField {
     A t = 0;
     int u = 0;
     acc_dot<UX>(t, u, xp, y);
-    if (u + UZ > kMaxU) {
+    if (u + uz_units(UZ) > kMaxU) {
       t = fp_fold(t, k);
-      u = 4;
+      u = kFoldU;
     }
     t = mad64(z, UZ == 3 ? zlift32 : zlift64, t);
-    return finish_dot<LAZY>(t, u + UZ);
+    return finish_dot<LAZY>(t, u + uz_units(UZ));
   }
 
   __device__ __forceinline__ void axpy(A* K, S c, const E* v) const {
@@ -142,11 +192,51 @@ struct FpField {
 #pragma unroll
     for (int i = 0; i < DL; ++i) K[i] = fp_fold(K[i], k);
   }
+
+  // Accumulator schedule of the register kernel.  General: the kernel folds
+  // at fixed places (fixed_fold) and kaxpy is a plain axpy.  Small fold
+  // constant: kaxpy folds only when the product class UP (units of 2^54)
+  // would pass the int64 budget, and fixed_fold does nothing.
+  template <int UP>
+  __device__ __forceinline__ void kaxpy(A* K, int& u, S c, const E* v) const {
+    if constexpr (SC) {
+      if (u + UP > kMaxU) {
+        fold(K);
+        u = kFoldU;
+      }
+      u += UP;
+    }
+    axpy(K, c, v);
+  }
+  template <int UP>
+  __device__ __forceinline__ void kmad(A& t, int& u, S a, S b) const {
+    if constexpr (SC) {
+      if (u + UP > kMaxU) {
+        t = fp_fold(t, k);
+        u = kFoldU;
+      }
+      u += UP;
+    }
+    t = mad64(a, b, t);
+  }
+  __device__ __forceinline__ void fixed_fold(A* K) const {
+    if constexpr (!SC) fold(K);
+  }
+
   __device__ __forceinline__ E finish(A K) const { return fp_redc2(fp_fold(K, k), k); }
   // finish(K) * c for a c carrying an extra factor 2^-32 (one 32-bit REDC step
-  // instead of a full one before the product)
+  // instead of a full one before the product).  Small fold constant: the
+  // product is finished with one more fold and 32-bit REDC step instead of
+  // REDC2 (c then carries 2^-64, see Inverses), leaving |J| <= h + 2^22.
   __device__ __forceinline__ E finish_mul32(A K, S c) const {
-    return fp_redc2(mul64(fp_redc1(fp_fold(K, k), k), c), k);
+    if constexpr (SC) return fp_redc1(fp_fold(mul64(fp_redc1(fp_fold(K, k), k), c), k), k);
+    else return fp_redc2(mul64(fp_redc1(fp_fold(K, k), k), c), k);
+  }
+  // small fold constant: a b 2^-32 mod p for |a|, |b| <= h + 2^23 (a product
+  // in the Montgomery domain of 2^32), result |.| <= h + 2^22
+  __device__ __forceinline__ S mulp(S a, S b) const {
+    static_assert(SC, "needs |2^32 mod p| <= 2^22");
+    return fp_redc1(fp_fold(mul64(a, b), k), k);
   }
   __device__ __forceinline__ E mul(E x, S c) const { return fp_mul(x, c, k); }
   __device__ __forceinline__ S smul(S a, S b) const { return fp_mul(a, b, k); }
@@ -228,6 +318,11 @@ struct C128Field {
     for (int i = 0; i < DL; ++i) K[i] = cmad(c, v[i], K[i]);
   }
   __device__ __forceinline__ void fold(A*) const {}
+  static constexpr bool kSC = false;
+  static constexpr int kPLazy = 0, kPLazyDiff = 0, kPBal = 0, kPBalDiff = 0;
+  template <int UP>
+  __device__ __forceinline__ void kaxpy(A* K, int&, S c, const E* v) const { axpy(K, c, v); }
+  __device__ __forceinline__ void fixed_fold(A*) const {}
   __device__ __forceinline__ E finish(A K) const { return K; }
   __device__ __forceinline__ E mul(E x, S c) const { return cmul(x, c); }
   __device__ __forceinline__ S smul(S a, S b) const { return cmul(a, b); }

@@ -80,8 +80,8 @@ struct LaunchArgs {
 template <class Fld>
 struct Loader;
 
-template <int DL, int L>
-struct Loader<FpField<DL, L>> {
+template <int DL, int L, bool SC>
+struct Loader<FpField<DL, L, SC>> {
   template <bool ALT = false>
   __device__ static int32_t get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                                 uint32_t& maxraw) {
@@ -136,34 +136,58 @@ struct Loader<C128Field<DL, L>> {
 template <class Fld, int NP>
 struct Inverses {};
 
-template <int DL, int L, int NP>
-struct Inverses<FpField<DL, L>, NP> {
+template <int DL, int L, bool SC, int NP>
+struct Inverses<FpField<DL, L, SC>, NP> {
   // Montgomery batch inversion (Montgomery 1987): one Fermat power for all NP
   // values; a zero anywhere makes the point singular.  inv(s) receives
-  // 2/P_S^2 for y(s) = -P_S^2.
+  // 2/P_S^2 for y(s) = -P_S^2, as the finish of each current expects it.
+  //
+  // General schedule: products are Montgomery products with R = 2^64 (fp_mul).
+  // Small fold constant: products are taken in the Montgomery domain of 2^32
+  // (mulp: a b 2^-32, one fold and one 32-bit REDC step), with 1 = 2^32 mod
+  // p.  There y(s) = -P^2 R stands for -P^2 2^32, so its inverse comes out as
+  // the plain residue -1/P^2, and the final product with the plain residue -2
+  // gives 2/P^2 2^-32, the extra 2^-32 that the small-fold finish needs.
   template <class Tab>
-  __device__ static bool compute(const FpField<DL, L>& F, int32_t (&y)[NP > 0 ? NP : 1], Tab& inv) {
+  __device__ static bool compute(const FpField<DL, L, SC>& F, int32_t (&y)[NP > 0 ? NP : 1], Tab& inv) {
     if constexpr (NP == 0) {
       return false;
     } else {
+      auto mul = [&](int32_t a, int32_t b) {
+        if constexpr (SC) return F.mulp(a, b);
+        else return fp_mul(a, b, F.k);
+      };
       bool zero = false;
       int32_t pre[NP];
 #pragma unroll
       for (int s = 0; s < NP; ++s) {
         if (y[s] == 0) { zero = true; y[s] = F.k.one; }
-        pre[s] = s == 0 ? y[0] : fp_mul(pre[s - 1], y[s], F.k);
+        pre[s] = s == 0 ? y[0] : mul(pre[s - 1], y[s]);
+      }
+      // a^(p-2) as straight-line code: 31 square-and-select steps, both
+      // products formed every step.  A few more products than a loop over the
+      // set bits, but the kernel stays one basic block, so the compiler keeps
+      // seeing its int32 values as sign-extended 32-bit operands (values
+      // carried across a loop were multiplied with the generic 64-bit sequence
+      // instead of one v_mad_i64_i32).
+      const uint32_t e = (uint32_t)(F.k.p - 2);
+      int32_t t = SC ? F.k.c32 : F.k.one;
+#pragma unroll
+      for (int b = 30; b >= 0; --b) {
+        t = mul(t, t);
+        const int32_t m = mul(t, pre[NP - 1]);
+        t = ((e >> b) & 1u) ? m : t;
       }
       // the factor -2 turns 1/y = -1/P^2 into 2/P^2 for every element.  It
       // is applied as the plain residue 2 (the constant 2 times R^-1), which
       // removes both the 2^32 that lazily reduced scalars leave in the current
       // accumulators and the 2^-32 of the single 32-bit REDC step that
       // finishes each current (FpField::finish_mul32)
-      int32_t t = fp_pow(pre[NP - 1], (uint32_t)(F.k.p - 2), F.k);
-      t = fp_mul(t, -2, F.k);
+      t = mul(t, -2);
 #pragma unroll
       for (int s = NP - 1; s >= 0; --s) {
-        inv.set(s, s == 0 ? t : fp_mul(t, pre[s - 1], F.k));
-        if (s > 0) t = fp_mul(t, y[s], F.k);
+        inv.set(s, s == 0 ? t : mul(t, pre[s - 1]));
+        if (s > 0) t = mul(t, y[s]);
       }
       return zero;
     }
@@ -288,9 +312,17 @@ struct Recursion {
           constexpr int i = decltype(ic)::value;
           constexpr int j = i + m - 1;
           E Pp[DL], P[DL];
-          primedP<i, j>(F, mom, Pp);
-          unprime(F, Pp, P);
-          y[R::pidx(i, j)] = F.ndot(Pp, P);
+          if constexpr (Fld::kSC) {
+            // P_S lazily normalised (|slot| <= h + 2^23): 66 units a product
+#pragma unroll
+            for (int c = 0; c < DL; ++c) P[c] = F.lazy_norm(Qg(j + 1, c) - Qg(i, c));
+            unprime(F, P, Pp);
+            y[R::pidx(i, j)] = F.template ndot<5>(Pp, P);
+          } else {
+            primedP<i, j>(F, mom, Pp);
+            unprime(F, Pp, P);
+            y[R::pidx(i, j)] = F.ndot(Pp, P);
+          }
         });
       });
       singular = Inverses<Fld, NP>::compute(F, y, inv);
@@ -329,6 +361,10 @@ struct Recursion {
         A K[DL];
 #pragma unroll
         for (int c = 0; c < DL; ++c) K[c] = F.azero();
+        // F_p, small fold constant: bound of K (and of nDacc) in units of
+        // 2^54; every loop here is unrolled, so these are compile-time
+        // constants and every fold decision is resolved at compile time
+        [[maybe_unused]] int uK = 0, uD = 0;
 
         // three-gluon vertex, A = [i..t], B = [t+1..j]
         S nDsum = F.szero();
@@ -348,10 +384,10 @@ struct Recursion {
             E Qt[DL];
 #pragma unroll
             for (int c = 0; c < DL; ++c) Qt[c] = Qg(t + 1, c);
-            F.axpy(K, F.sneg(nDm), Qt);
-            F.axpy(K, F.sneg(nc2), J[ib]);
-            F.axpy(K, nc3, J[ia]);
-            F.fold(K);
+            F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nDm), Qt);
+            F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nc2), J[ib]);
+            F.template kaxpy<Fld::kPLazy>(K, uK, nc3, J[ia]);
+            F.fixed_fold(K);
           } else {
 #pragma unroll
             for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? Qg(i, c) : F.eadd(PA[c], Qg(t, c));
@@ -366,10 +402,14 @@ struct Recursion {
             F.axpy(K, n3, J[ia]);
           }
           if constexpr (kFp) {
-            // products below 3 half-units (lazy nDm times balanced 1/2): fold
-            // before every third one after the first three
-            if constexpr (t > i && (t - i) % 3 == 0) nDacc = fp_fold(nDacc, F.k);
-            nDacc = mad64(nDm, F.k.inv2, nDacc);
+            if constexpr (Fld::kSC) {
+              F.template kmad<Fld::kPLazy>(nDacc, uD, nDm, F.k.inv2);
+            } else {
+              // products below 3 half-units (lazy nDm times balanced 1/2): fold
+              // before every third one after the first three
+              if constexpr (t > i && (t - i) % 3 == 0) nDacc = fp_fold(nDacc, F.k);
+              nDacc = mad64(nDm, F.k.inv2, nDacc);
+            }
           } else {
             nDsum = accumulate_scalar(F, nDsum, nDm);
           }
@@ -382,8 +422,8 @@ struct Recursion {
           E QQ[DL];
 #pragma unroll
           for (int c = 0; c < DL; ++c) QQ[c] = Qg(i, c) + Qg(j + 1, c);
-          F.axpy(K, nDhS, QQ);
-          F.fold(K);
+          F.template kaxpy<Fld::kPBalDiff>(K, uK, nDhS, QQ);
+          F.fixed_fold(K);
         } else {
           nDhS = half_scalar(F, nDsum);
         }
@@ -395,24 +435,25 @@ struct Recursion {
           static_for<s1 + 1, j>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
             const S ne = F.template ndot_u<kFp>(J[R::idx(i, s1)], J[R::idx(t + 1, j)]);  // F_p: lazy
-            F.axpy(K, F.sneg(ne), J[R::idx(s1 + 1, t)]);
+            F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(ne), J[R::idx(s1 + 1, t)]);
             constexpr int qn = v4_index<i, j>(s1, t);
-            // F_p: lazy scalars give products below 3 half-units: fold every third
-            if constexpr (kFp ? (qn % 3 == 2) : (qn % 5 == 4)) F.fold(K);
+            // F_p, general schedule: lazy scalars give products below 3
+            // half-units: fold every third
+            if constexpr (qn % 3 == 2) F.fixed_fold(K);
             split_barrier();
           });
         });
-        F.fold(K);
+        F.fixed_fold(K);
         static_for<i + 1, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
-          F.axpy(K, nDh.get(R::pidx(i, t)), J[R::idx(t + 1, j)]);
-          if constexpr ((t - i) % 5 == 4) F.fold(K);
+          F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(i, t)), J[R::idx(t + 1, j)]);
+          if constexpr ((t - i) % 5 == 4) F.fixed_fold(K);
         });
-        F.fold(K);
+        F.fixed_fold(K);
         static_for<i, j - 1>([&](auto sc) {
           constexpr int s1 = decltype(sc)::value;
-          F.axpy(K, nDh.get(R::pidx(s1 + 1, j)), J[R::idx(i, s1)]);
-          if constexpr ((s1 - i) % 5 == 4) F.fold(K);
+          F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(s1 + 1, j)), J[R::idx(i, s1)]);
+          if constexpr ((s1 - i) % 5 == 4) F.fixed_fold(K);
         });
 
         if constexpr (!root) {

@@ -45,9 +45,13 @@ __global__ __launch_bounds__(kBlock) void issue_kernel(uint64_t* sink, int iters
       } else if constexpr (KIND == BG_PROBE_FMA_F64) {
         facc[c] = __builtin_fma(facc[c], 0.9999999, 0x1.0p-30);
       } else if constexpr (KIND == BG_PROBE_MUL_LO_U32) {
-        x[c] = x[c] * b;
+        // a squaring chain: a constant factor would let the compiler merge
+        // the unrolled rounds (x b b b b = x b^4) and count one multiply as four
+        x[c] = x[c] * x[c];
       } else {  // BG_PROBE_DPP_MOV_B32
-        x[c] = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[c], 0xB1, 0xF, 0xF, false);
+        // row_ror:1 (a pair swap applied twice is the identity, which the
+        // compiler removes)
+        x[c] = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[c], 0x121, 0xF, 0xF, false);
       }
     }
   }

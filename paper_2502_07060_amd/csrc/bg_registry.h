@@ -28,7 +28,13 @@ struct Variant {
   unsigned (*lds_per_point)(int N) = nullptr;  // runtime-n kernels: LDS bytes per point
   bool padded = false;  // lane-group kernel whose table rows are padded to an odd number of 16-byte units
   int split = 1;        // lane-group kernel: lanes per work item (DL / split components each)
+  // Z_p register kernel compiled for the small-fold-constant schedule (primes
+  // with |2^32 mod p| <= 2^22); the launch takes it instead of fn for those
+  const void* fn_sc = nullptr;
 };
+
+// |2^32 mod p| (balanced) <= 2^22: the small-fold-constant schedule applies
+inline bool fp_small_fold(const FpConst& k) { return k.c32 >= -(1 << 22) && k.c32 <= (1 << 22); }
 
 std::vector<Variant>& registry();
 bool is_pinned(int field, int n, int d);
@@ -81,6 +87,18 @@ unsigned wide_lds_bytes(int N) {
   static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                                   \
       FIELDTAG, N_, DL_, L_, 256, false, LT_, W_,                                                       \
       reinterpret_cast<const void*>(&bg_recursion_kernel<FLD<DL_, L_>, N_, DL_, L_, 256, LT_, W_>)});   \
+  }
+
+// the same for Z_p: both reduction schedules, selected per launch by the prime
+#define BG_REGISTER_RECURSION_FP(N_, DL_, L_, LT_, W_)                                                       \
+  namespace bg {                                                                                             \
+  template __global__ void bg_recursion_kernel<FpField<DL_, L_, false>, N_, DL_, L_, 256, LT_, W_>(LaunchArgs); \
+  template __global__ void bg_recursion_kernel<FpField<DL_, L_, true>, N_, DL_, L_, 256, LT_, W_>(LaunchArgs);  \
+  static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                                        \
+      FIELD_FP, N_, DL_, L_, 256, false, LT_, W_,                                                            \
+      reinterpret_cast<const void*>(&bg_recursion_kernel<FpField<DL_, L_, false>, N_, DL_, L_, 256, LT_, W_>), \
+      nullptr, false, 1,                                                                                     \
+      reinterpret_cast<const void*>(&bg_recursion_kernel<FpField<DL_, L_, true>, N_, DL_, L_, 256, LT_, W_>)}); \
   }
 
 #define BG_REGISTER_GENERIC(FIELDTAG, FLD, DMAX_)                                               \

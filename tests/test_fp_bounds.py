@@ -84,6 +84,26 @@ def _c32_extreme_prime(sign):
     return best[1]
 
 
+def _sc_extreme_prime(sign):
+    """The prime whose balanced fold constant 2^32 mod p is the largest
+    (sign +1) or the most negative (sign -1) value the small-fold-constant
+    schedule accepts, |2^32 mod p| <= 2^22.  For p = 2^31 - c (c <= 2^21) the
+    constant is 2c; just above 2^32 / 3 it is -(3p - 2^32)."""
+    if sign > 0:
+        p = 2**31 - 2**21
+        while not is_prime(p):
+            p += 1
+        return p
+    p = -(-2**32 // 3) + 2**22 // 3
+    while not is_prime(p):
+        p -= 1
+    return p
+
+
+def small_fold(p):
+    return abs(balanced(2**32, p)) <= 2**22
+
+
 PRIMES = sorted({
     2**31 - 1,                     # Mersenne: the largest h
     2147483629,                    # 2^31 - 19, the default prime
@@ -366,6 +386,143 @@ def replay_register_kernel(p, N, DL, L):
     return worst
 
 
+# ---------------------------------------------------------------------------
+# register kernel, small-fold-constant schedule (|2^32 mod p| <= 2^22): units
+# of 2^54, an int64 holds 511, a fold leaves 1; the current accumulators are
+# folded only when the next product would pass the budget
+# ---------------------------------------------------------------------------
+class FieldModelSC:
+    """The dot-product helpers of FpField<DL, L, true>: fold decisions mirror
+    the device code's unit counter; the bound is exact."""
+
+    MAXU = 511
+    FOLDU = 1
+    LAZYIN = 2
+    REDC2IN = 256
+
+    def __init__(self, B: Bounds, DL, L):
+        self.B, self.DL, self.L = B, DL, L
+        assert small_fold(B.p)
+
+    @staticmethod
+    def ux_units(UX):
+        return 129 if UX == 4 else 66
+
+    def acc_dot(self, t, u, bx, by, UX):
+        for _ in range(self.DL):
+            if u + self.ux_units(UX) > self.MAXU:
+                t, u = self.B.fold(t), self.FOLDU
+            t = self.B.chk(t + bx * by, "acc_dot")
+            u += self.ux_units(UX)
+        return t, u
+
+    def finish_dot(self, t, u, lazy):
+        L = self.L
+        if L > 1:
+            if L * u > self.MAXU:
+                t, u = self.B.fold(t), self.FOLDU
+            t = self.B.chk(L * t, "group sum")
+            u *= L
+        if lazy:
+            if u > self.LAZYIN:
+                t = self.B.fold(t)
+            return self.B.redc1(t)
+        if u >= self.REDC2IN:
+            t = self.B.fold(t)
+        return self.B.redc2(t)
+
+    def ndot(self, bx, by, UX=2, lazy=False):
+        t, u = self.acc_dot(0, 0, bx, by, UX)
+        return self.finish_dot(t, u, lazy)
+
+    def ndot_sub(self, bx, by, bz, UX=2, UZ=2, lazy=False):
+        t, u = self.acc_dot(0, 0, bx, by, UX)
+        uz = 1 if UZ == 3 else 64
+        if u + uz > self.MAXU:
+            t, u = self.B.fold(t), self.FOLDU
+        lift = abs(self.B.k.c32) if UZ == 3 else abs(self.B.k.c64)
+        t = self.B.chk(t + bz * lift, "ndot_sub lift")
+        return self.finish_dot(t, u + uz, lazy)
+
+
+class TrackedVec(Vec):
+    """A current accumulator under the small-fold schedule (kaxpy)."""
+
+    def __init__(self, B: Bounds):
+        super().__init__(B)
+        self.u = 0
+
+    def kaxpy(self, UP, bc, bv):
+        if self.u + UP > FieldModelSC.MAXU:
+            self.fold()
+            self.u = FieldModelSC.FOLDU
+        self.u += UP
+        self.axpy(bc, bv)
+
+
+def replay_register_kernel_sc(p, N, DL, L):
+    B = Bounds(p)
+    F = FieldModelSC(B, DL, L)
+    h = B.h
+    nb = h + 2**23             # the bound the unit counts assume for currents and lazy scalars
+    lazyP = 2 * h              # Q_{j+1} - Q_i, unreduced
+    # legs: nc(l) = -(k_l . eps_l), lazily reduced
+    nc = F.ndot(h, h, UX=2, lazy=True)
+    assert nc <= nb
+    # propagators: P lazily normalised (one product with 2^32 mod p, one
+    # 32-bit REDC step), y = -(P.P) reduced by REDC2
+    Pn = B.redc1(B.chk(lazyP * abs(B.k.c32), "lazy_norm"))
+    assert Pn <= nb
+    ybound = F.ndot(Pn, Pn, UX=5, lazy=False)
+    # batched inversion in the Montgomery domain of 2^32: mulp = fold and one
+    # 32-bit REDC step of a product; factors are y (balanced), the running
+    # products, the powers and the plain residue -2
+    def mulp(a, b):
+        return B.redc1(B.fold(B.chk(a * b, "mulp")))
+    v = max(ybound, abs(B.k.c32))
+    for _ in range(4):          # the running values' bound reaches its fixed point
+        v = max(v, mulp(v, max(v, ybound)), mulp(v, 2))
+    inv = v
+    assert inv <= nb
+    for j in range(1, N):
+        for i in range(j - 1, -1, -1):
+            root = i == 0 and j == N - 1
+            K = TrackedVec(B)
+            nDacc, uD = 0, 0
+            for t in range(i, j):
+                nDm = F.ndot(nb, nb, UX=2, lazy=True)
+                nc2 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
+                nc3 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
+                assert max(nDm, nc2, nc3) <= nb
+                K.kaxpy(66, nDm, h)       # times Q_{t+1} (balanced)
+                K.kaxpy(66, nc2, nb)      # times J_B
+                K.kaxpy(66, nc3, nb)      # times J_A
+                if uD + 66 > FieldModelSC.MAXU:
+                    nDacc, uD = B.fold(nDacc), FieldModelSC.FOLDU
+                uD += 66
+                nDacc = B.chk(nDacc + nDm * h, "nDacc")   # times the constant 1/2
+            nDhS = B.redc2(B.fold(nDacc))
+            K.kaxpy(128, nDhS, 2 * h)     # times Q_i + Q_{j+1}, unreduced
+            for s1 in range(i, j - 1):
+                for t in range(s1 + 1, j):
+                    ne = F.ndot(nb, nb, UX=2, lazy=True)
+                    K.kaxpy(66, ne, nb)
+            for _t in range(i + 1, j):
+                K.kaxpy(65, h, nb)        # nDh (balanced) times J
+            for _s1 in range(i, j - 1):
+                K.kaxpy(65, h, nb)
+            if not root:
+                s = B.redc1(B.fold(K.b))                  # finish_mul32, small fold
+                J = B.redc1(B.fold(B.chk(s * inv, "finish product")))
+                assert J <= nb
+                nc = max(nc, F.ndot(lazyP, nb, UX=4, lazy=True))
+                assert nc <= nb
+            else:
+                B.redc2(B.fold(K.b))                      # finish
+                F.ndot(h, h, UX=2, lazy=False)            # eps_n . K
+    B.redc2(h * h)
+
+
 # every register-kernel instantiation of the build list
 def _register_variants():
     from paper_2502_07060_amd import build as b
@@ -378,6 +535,30 @@ def test_register_kernel_schedule(p):
     assert variants, "no Z_p register kernels in the build list"
     for N, DL, L in variants:
         replay_register_kernel(p, N, DL, L)
+
+
+@pytest.mark.parametrize("p", [2**31 - 1, 2147483629, _sc_extreme_prime(+1), _sc_extreme_prime(-1), 65537, 13])
+def test_register_kernel_small_fold_schedule(p):
+    assert small_fold(p)
+    for N, DL, L in _register_variants():
+        replay_register_kernel_sc(p, N, DL, L)
+
+
+def test_small_fold_replay_catches_a_wider_fold_constant():
+    """The small-fold schedule relies on |2^32 mod p| <= 2^22: at a prime whose
+    constant is near h the same fold decisions overflow."""
+    p = _c32_extreme_prime(+1)
+    B = Bounds(p)
+    with pytest.raises(AssertionError):
+        F = FieldModelSC.__new__(FieldModelSC)
+        F.B, F.DL, F.L = B, 6, 1
+        h = B.h
+        K = TrackedVec(B)
+        for _ in range(16):
+            K.kaxpy(66, h + 2**23, h + 2**23)
+        B.redc1(B.fold(K.b))
+        nDm = F.ndot(h, h, UX=2, lazy=True)
+        assert nDm <= h + 2**23
 
 
 def test_register_kernel_replay_catches_a_missing_fold():

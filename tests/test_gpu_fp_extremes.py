@@ -17,9 +17,10 @@ h = (p - 1) / 2, so x = h and x = h + 1 give +h and -h.
 * draws from {0, 1, 2, h - 1, h, h + 1, h + 2, p - 2, p - 1} per component.
 
 Every compiled kernel variant of each (n, d) is compared with the oracle bit
-for bit, statuses included, at four primes: 2^31 - 1 (largest h),
-2^31 - 19 (the default) and the two primes below 2^31 whose fold constant
-2^32 mod p is closest to +h and to -h.
+for bit, statuses included, at six primes: 2^31 - 1 (largest h),
+2^31 - 19 (the default), the two primes whose fold constant 2^32 mod p is the
+widest the small-fold-constant schedule accepts (+-2^22), and the two primes
+below 2^31 whose fold constant is closest to +h and to -h (general schedule).
 """
 import numpy as np
 import pytest
@@ -27,12 +28,16 @@ import pytest
 from paper_2502_07060_amd import bg
 
 import bgtest
-from test_fp_bounds import _c32_extreme_prime
+from test_fp_bounds import _c32_extreme_prime, _sc_extreme_prime
 from test_gpu_parity import assert_fp_equal, gpu_fp, torch_dev  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
-PRIMES = [2**31 - 1, 2147483629, _c32_extreme_prime(+1), _c32_extreme_prime(-1)]
+# 2^31 - 1 and 2^31 - 19 and the two primes with the widest fold constants the
+# small-fold-constant schedule accepts run that schedule; the two primes with
+# fold constants near +-h run the general one
+PRIMES = [2**31 - 1, 2147483629, _sc_extreme_prime(+1), _sc_extreme_prime(-1),
+          _c32_extreme_prime(+1), _c32_extreme_prime(-1)]
 
 
 def extreme_inputs(seed, n, d, npts, p):
