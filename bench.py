@@ -251,6 +251,46 @@ def run_workload(kind: str, steps: int, warmup: int, int_peak_tops: float | None
     }
 
 
+def run_group(spec: str, steps: int, warmup: int):
+    """One group of the batched workload alone, e.g. "c128:14:6" (the group's
+    size and seed from the batched draw) or "fp:12:8:65536" (that many points,
+    same generator): autotuned at its size, then timed like the n = 8
+    workloads.  Used to profile the runtime-n kernels one group at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07060_amd import bg
+    from paper_2502_07060_amd import inputs as I
+
+    parts = spec.split(":")
+    field, n, d = parts[0], int(parts[1]), int(parts[2])
+    g = next(dict(x) for x in I.batched_groups() if (x["field"], x["n"], x["d"]) == (field, n, d))
+    if len(parts) > 3:
+        g["npts"] = int(parts[3])
+    p = I.DEFAULT_PRIME
+    k, e = I.group_inputs(g, p)
+    dev = torch.device("cuda:0")
+    npts = g["npts"]
+    fid = bg.BG_FIELD_FP if field == "fp" else bg.BG_FIELD_C128
+    chosen, tuned = bg.bg_autotune(fid, n, d, p if field == "fp" else 0, npts=npts, reps=5)
+    if field == "fp":
+        tk = torch.from_numpy(I.to_soa(k.astype(np.uint32)).view(np.int32)).to(dev)
+        te = torch.from_numpy(I.to_soa(e.astype(np.uint32)).view(np.int32)).to(dev)
+        fn = lambda: bg.bg_amplitudes_fp(tk, te, p)
+    else:
+        tk = torch.from_numpy(I.to_soa(k.astype(np.complex128))).to(dev)
+        te = torch.from_numpy(I.to_soa(e.astype(np.complex128))).to(dev)
+        fn = lambda: bg.bg_amplitudes_c128(tk, te)
+    total_ms, launch_ms, _ = time_launches(fn, steps, warmup)
+    roof = group_roofline_ms(field, n, d, npts)
+    return {"workload": f"batched group {field} n={n} d={d}, {npts} points (seed {g['seed']})",
+            "npts": npts, "kernel_ms": launch_ms, "ms_per_step": total_ms / steps,
+            "value": npts / (launch_ms * 1e-3), "unit": "amplitudes/s",
+            "roofline_ms": roof, "frac": roof / launch_ms,
+            "variant": next({kk: v[kk] for kk in ("lanes", "comps_per_lane", "lds_tables", "generic", "padded")}
+                            for v, _ in tuned if v["index"] == chosen)}
+
+
 def run_alternating(kind: str, steps: int, warmup: int, mostly_minus_ms: float):
     """The same workload through bg_amplitudes_*_metric in the alternating
     metric of Sec. 3.1 (the loaders map it onto the mostly-minus one), against
@@ -824,6 +864,8 @@ def main(argv=None):
                                            "states", "rational", "ffops", "cut"],
                     default="both",
                     help="restrict to one workload (profiling runs)")
+    ap.add_argument("--group", metavar="FIELD:N:D[:NPTS]",
+                    help="time one group of the batched workload alone (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one device-to-device copy of MIB MiB: a plain copy "
                          "kernel of known traffic that scales hardware byte counters")
@@ -835,6 +877,11 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if a.group:
+        r = run_group(a.group, a.steps, a.warmup)
+        calibrate_copy(a.calibrate_copy)
+        print(json.dumps(r), flush=True)
+        return
     if a.workload == "batched":
         print(json.dumps(run_batched(a.steps, a.warmup)), flush=True)
         return

@@ -37,6 +37,11 @@
 #ifndef BG_SPLIT_BARRIER
 #define BG_SPLIT_BARRIER 1
 #endif
+// instruction classes the scheduler may still move across a split barrier
+// (sched_barrier mask; 0: none)
+#ifndef BG_SPLIT_BARRIER_MASK
+#define BG_SPLIT_BARRIER_MASK 0
+#endif
 
 namespace bg {
 
@@ -370,27 +375,46 @@ struct Recursion {
         S nDsum = F.szero();
         [[maybe_unused]] int64_t nDacc = 0;  // F_p: sum of -(J_A.J_B) * (1/2), unreduced
         [[maybe_unused]] E PA[DL];
+        // The LDS operands of a split (complex: k'_t; F_p: Q_{t+1}, c(A),
+        // c(B)) are read one split ahead, inside the previous split's
+        // scheduling region: with one wave per SIMD the read latency is
+        // otherwise exposed at the start of every split.
+        struct SplitLds {
+          E v[DL];
+          S ca, cb;
+        };
+        auto lds_of = [&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          SplitLds o;
+#pragma unroll
+          for (int c = 0; c < DL; ++c) o.v[c] = kFp ? Qg(t + 1, c) : Qg(t, c);
+          if constexpr (kFp) {
+            o.ca = nc.get(R::idx(i, t));
+            o.cb = nc.get(R::idx(t + 1, j));
+          }
+          return o;
+        };
+        SplitLds next = lds_of(std::integral_constant<int, i>{});
         static_for<i, j>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
           constexpr int ia = R::idx(i, t), ib = R::idx(t + 1, j);
+          const SplitLds cur = next;
+          if constexpr (t + 1 < j) next = lds_of(std::integral_constant<int, t + 1>{});
           // -(J_A.J_B); F_p: lazily reduced (it only multiplies balanced values)
           const S nDm = F.template ndot_u<kFp>(J[ia], J[ib]);
           if constexpr (kFp) {
             // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
             // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
             // lazy P_S slots, lazy stored P_X.J_X, lazily reduced results
-            const S nc2 = F.template ndot_sub<4, 3, true>(Pp, J[ia], nc.get(ia));   // -(P_B.J_A)
-            const S nc3 = F.template ndot_sub<4, 3, true>(Pp, J[ib], nc.get(ib));   // -(P_A.J_B)
-            E Qt[DL];
-#pragma unroll
-            for (int c = 0; c < DL; ++c) Qt[c] = Qg(t + 1, c);
-            F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nDm), Qt);
+            const S nc2 = F.template ndot_sub<4, 3, true>(Pp, J[ia], cur.ca);   // -(P_B.J_A)
+            const S nc3 = F.template ndot_sub<4, 3, true>(Pp, J[ib], cur.cb);   // -(P_A.J_B)
+            F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nDm), cur.v);          // times Q_{t+1}
             F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nc2), J[ib]);
             F.template kaxpy<Fld::kPLazy>(K, uK, nc3, J[ia]);
             F.fixed_fold(K);
           } else {
 #pragma unroll
-            for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? Qg(i, c) : F.eadd(PA[c], Qg(t, c));
+            for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? cur.v[c] : F.eadd(PA[c], cur.v[c]);
             const S n2 = F.ndot(col[t + 1], J[ia]);        // -(P_B.J_A)
             const S n3 = F.ndot(PA, J[ib]);                // -(P_A.J_B)
             E v[DL];
@@ -500,7 +524,7 @@ struct Recursion {
   // turns into spills.
   __device__ static __forceinline__ void split_barrier() {
 #if BG_SPLIT_BARRIER
-    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(BG_SPLIT_BARRIER_MASK);
 #endif
   }
 
