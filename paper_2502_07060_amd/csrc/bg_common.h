@@ -21,6 +21,24 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware block order.  The workgroups of a launch go to the device's 8
+// XCDs in turn (workgroup b to XCD b mod 8), and each XCD has its own L2.  A
+// kernel whose block reads less than a cache line of every input row (a few
+// points per block, the point index fastest in memory) renumbers its blocks
+// so that consecutive point ranges run on one XCD: the blocks that share a
+// line then share one L2, and the line comes from HBM once instead of once
+// per XCD.  The renumbering is a bijection of [0, gridDim.x) whatever the
+// hardware's actual placement, so it affects only where data is cached.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xcd_block_index() {
+  constexpr uint32_t X = 8;
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  const uint32_t per = nb / X, rem = nb % X;
+  const uint32_t x = b % X, k = b / X;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// ---------------------------------------------------------------------------
 // sub-range bookkeeping for N = n - 1 legs (0-based i <= j < N)
 // ---------------------------------------------------------------------------
 template <int N>

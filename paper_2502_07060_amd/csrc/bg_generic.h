@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void bg_generic_kernel(LaunchArgs a, int N) {
   extern __shared__ __align__(16) char lds[];
   const int P = blockDim.x;
   const int t = threadIdx.x;
-  const int64_t q0 = (int64_t)blockIdx.x * P + t;
+  const int64_t q0 = (int64_t)xcd_block_index() * P + t;
   const bool valid = q0 < a.npts;
   const int64_t q = valid ? q0 : a.npts - 1;
   uint32_t bad = 0;

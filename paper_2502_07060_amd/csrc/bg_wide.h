@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
   static_assert(G >= 16 && 64 % GL == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
   const int t = (int)(threadIdx.x % GL);
   const int pb = (int)(threadIdx.x / GL);
-  const int64_t q0 = (int64_t)blockIdx.x * (blockDim.x / GL) + pb;
+  const int64_t q0 = (int64_t)xcd_block_index() * (blockDim.x / GL) + pb;
   const bool valid = q0 < a.npts;
   const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
   WR W(lds + (size_t)pb * Lay::offsets(N).total, N, t);
