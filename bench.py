@@ -623,8 +623,23 @@ def run_batched(steps: int, warmup: int):
     finally:
         plan.close()
     bad += sum(int((tens[i][3] != 0).sum().item()) for i in range(len(groups)))
+    # queue form: one persistent launch per lane-group kernel variant over a
+    # device work queue, as a call and as a graph plan
+    for i in range(len(groups)):
+        tens[i][3].fill_(9)
+    runq = lambda: bg.bg_batch_run_ex(descs, bg.BG_BATCH_QUEUE)
+    _, q_launch_ms, _ = time_launches(runq, steps, warmup)
+    bad += sum(int((tens[i][3] != 0).sum().item()) for i in range(len(groups)))
+    for i in range(len(groups)):
+        tens[i][3].fill_(9)
+    qplan = bg.BatchPlan(descs, bg.BG_BATCH_QUEUE)
+    try:
+        _, qp_launch_ms, _ = time_launches(qplan.launch, steps, warmup)
+    finally:
+        qplan.close()
+    bad += sum(int((tens[i][3] != 0).sum().item()) for i in range(len(groups)))
     roof_ms = sum(group_roofline_ms(g["field"], g["n"], g["d"], g["npts"]) for g in groups)
-    best = min(launch_ms, p_launch_ms)
+    best = min(launch_ms, p_launch_ms, q_launch_ms, qp_launch_ms)
     # each group alone (same kernels), to show where the time goes
     per_group = []
     for i, g in enumerate(groups):
@@ -641,6 +656,7 @@ def run_batched(steps: int, warmup: int):
                     "Zipf(1.2) group sizes, seed 4",
         "value": total / (best * 1e-3), "unit": "amplitudes/s", "npts": total, "groups": len(groups),
         "ms_batch_run": launch_ms, "ms_graph_plan": p_launch_ms,
+        "ms_queue_run": q_launch_ms, "ms_queue_graph_plan": qp_launch_ms,
         "roofline": {"bound": "mixed (per group max of HBM and ALU time)", "roofline_ms": roof_ms,
                      "measured_ms": best, "frac": roof_ms / best},
         "nonzero_status": bad, "host_generation_s": t_gen, "autotune_s": t_tune,

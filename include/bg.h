@@ -325,13 +325,36 @@ typedef struct {
 int bg_batch_run(const bg_group* groups, int ngroups, void* hip_stream);
 
 /*
+ * The same call with options.  BG_BATCH_QUEUE: every group whose selected
+ * kernel is a lane-group (runtime-n) kernel is served by one persistent launch
+ * per such kernel variant instead of one launch per group.  Its blocks stay
+ * resident and take (group, point range) tiles from a device work queue, the
+ * groups ordered by work per point, longest first; register-kernel groups run
+ * as in bg_batch_run.  The queue's counters and group table (about 160 bytes
+ * a group) are device memory this call allocates stream-ordered on
+ * hip_stream and frees after its launches.  Results equal bg_batch_run's bit
+ * for bit (same kernels, same arithmetic per point).  flags = 0 is
+ * bg_batch_run.  Errors: as bg_batch_run, BG_EINVAL for unknown flags,
+ * BG_ENOMEM if the queue memory cannot be allocated.
+ */
+#define BG_BATCH_QUEUE 1
+int bg_batch_run_ex(const bg_group* groups, int ngroups, int flags, void* hip_stream);
+
+
+/*
  * A batch plan records the launches of a fixed set of groups (pointers and
  * sizes fixed, kernel variants as selected at creation) as one hipGraph of
  * independent kernel nodes; bg_batch_plan_launch replays it on hip_stream with
- * a single graph launch.  Plans own no device memory.
+ * a single graph launch.  Plans own no device memory (but see
+ * bg_batch_plan_create_ex).
  */
 typedef struct bg_batch_plan bg_batch_plan;
 int bg_batch_plan_create(const bg_group* groups, int ngroups, bg_batch_plan** plan);
+/* flags as bg_batch_run_ex: with BG_BATCH_QUEUE the plan owns the queue's
+ * device memory (allocated and written at creation, freed by destroy) and
+ * each replay zeroes the counters with a kernel node before the persistent
+ * launches. */
+int bg_batch_plan_create_ex(const bg_group* groups, int ngroups, int flags, bg_batch_plan** plan);
 int bg_batch_plan_launch(bg_batch_plan* plan, void* hip_stream);
 int bg_batch_plan_destroy(bg_batch_plan* plan);
 

@@ -25,6 +25,7 @@ BG_PT_OK, BG_PT_SINGULAR, BG_PT_BADRESIDUE = 0, 1, 2
 BG_FIELD_C128, BG_FIELD_FP = 0, 1
 BG_METRIC_MOSTLY_MINUS, BG_METRIC_ALTERNATING = 0, 1
 BG_MAX_N, BG_MAX_D = 14, 10
+BG_BATCH_QUEUE = 1
 (BG_PROBE_MAD_I64_I32, BG_PROBE_MAD_U64_U32, BG_PROBE_FMA_F64, BG_PROBE_MUL_LO_U32,
  BG_PROBE_DPP_MOV_B32) = range(5)
 FP_SENTINEL = 0xFFFFFFFF
@@ -80,7 +81,9 @@ _SIGNATURES = {
     "bg_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "bg_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bg_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_batch_run_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_batch_plan_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bg_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "bg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]),
@@ -571,16 +574,23 @@ def bg_batch_run(groups, stream=None) -> None:
         raise BGError(rc, "bg_batch_run")
 
 
+def bg_batch_run_ex(groups, flags=0, stream=None) -> None:
+    arr = _group_array(groups)
+    rc = lib().bg_batch_run_ex(ctypes.cast(arr, ctypes.c_void_p), len(groups), int(flags), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_batch_run_ex")
+
+
 class BatchPlan:
     """A recorded batch (hipGraph); launch() replays it on a stream."""
 
-    def __init__(self, groups):
+    def __init__(self, groups, flags=0):
         self._groups = _group_array(groups)   # keep the descriptors alive with the plan
         self._h = ctypes.c_void_p()
-        rc = lib().bg_batch_plan_create(ctypes.cast(self._groups, ctypes.c_void_p), len(groups),
-                                        ctypes.byref(self._h))
+        rc = lib().bg_batch_plan_create_ex(ctypes.cast(self._groups, ctypes.c_void_p), len(groups), int(flags),
+                                           ctypes.byref(self._h))
         if rc != BG_OK:
-            raise BGError(rc, "bg_batch_plan_create")
+            raise BGError(rc, "bg_batch_plan_create_ex")
 
     def launch(self, stream=None) -> None:
         rc = lib().bg_batch_plan_launch(self._h, _stream_ptr(stream))

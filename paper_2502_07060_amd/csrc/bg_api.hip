@@ -131,7 +131,6 @@ static int pinned(int field, int n, int d) {
 bool is_pinned(int field, int n, int d) { return pinned(field, n, d) >= 0; }
 
 const Variant* default_variant(int field, int n, int d);
-static int max_lds_per_block();
 
 // a wide kernel keeps at least 512 lanes (8 waves) busy per CU at this N
 static bool best_fills(const Variant* v, int N) {
@@ -185,7 +184,7 @@ const Variant* default_variant(int field, int n, int d) {
   return nullptr;
 }
 
-static int max_lds_per_block() {
+int max_lds_per_block() {
   static std::once_flag once;
   static int v = 65536;
   std::call_once(once, [] {
@@ -214,6 +213,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.metric = BG_METRIC_MOSTLY_MINUS;
   a.ialt = 0;
   a.cur = nullptr;
+  spec.variant = v;
   spec.fn = (field == FIELD_FP && v->fn_sc && fp_small_fold(fp)) ? v->fn_sc : v->fn;
   spec.generic = v->generic;
   spec.lanes = v->L;
@@ -235,15 +235,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
     P = (int)std::min<size_t>(256, (size_t)maxlds / per);
     if (P >= 64) P = P / 64 * 64;
   } else {
-    // G lanes per point: the block size whose blocks hold the most points per CU
-    const int pmax = std::min<int>(256 / v->L, (int)((size_t)maxlds / per));
-    P = 1;
-    long bestres = 0;
-    for (int c = 1; c <= pmax; ++c) {
-      const long blocks = std::min<long>((long)maxlds / ((long)c * (long)per), 2048 / ((long)c * v->L));
-      const long res = blocks * c;
-      if (res > bestres || (res == bestres && c > P)) { bestres = res; P = c; }
-    }
+    P = wide_points_per_block(*v, per);
   }
   if (P < 1) return BG_ENOTIMPL;
   const size_t shmem = per * P;
@@ -258,6 +250,20 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   spec.block = (unsigned)(P * v->L);
   spec.shmem = (unsigned)shmem;
   return BG_OK;
+}
+
+int wide_points_per_block(const Variant& v, size_t per) {
+  // G lanes per point: the block size whose blocks hold the most points per CU
+  const int maxlds = max_lds_per_block();
+  const int pmax = std::min<int>(256 / v.L, (int)((size_t)maxlds / per));
+  int P = 1;
+  long bestres = 0;
+  for (int c = 1; c <= pmax; ++c) {
+    const long blocks = std::min<long>((long)maxlds / ((long)c * (long)per), 2048 / ((long)c * v.L));
+    const long res = blocks * c;
+    if (res > bestres || (res == bestres && c > P)) { bestres = res; P = c; }
+  }
+  return P;
 }
 
 int enqueue(LaunchSpec& spec, hipStream_t stream) {

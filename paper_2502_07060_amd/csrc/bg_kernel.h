@@ -65,6 +65,16 @@ struct LaunchArgs {
   void* cur;
 };
 
+// One group of a persistent queue launch (bg_wide_queue_kernel): its launch
+// arguments, N = n - 1, and the first tile of the group in queue order (tiles
+// of a fixed number of points per launch).
+struct QueueGroup {
+  LaunchArgs args;
+  int N;
+  uint32_t first_tile;
+};
+constexpr unsigned kQueueLdsHeader = 16;  // LDS bytes before the points' tables
+
 // ---------------------------------------------------------------------------
 // loads
 // ---------------------------------------------------------------------------

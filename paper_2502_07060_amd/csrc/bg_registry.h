@@ -31,6 +31,8 @@ struct Variant {
   // Z_p register kernel compiled for the small-fold-constant schedule (primes
   // with |2^32 mod p| <= 2^22); the launch takes it instead of fn for those
   const void* fn_sc = nullptr;
+  // lane-group kernel: its persistent work-queue form (bg_wide_queue_kernel)
+  const void* fn_queue = nullptr;
 };
 
 // |2^32 mod p| (balanced) <= 2^22: the small-fold-constant schedule applies
@@ -42,6 +44,7 @@ bool is_pinned(int field, int n, int d);
 // A fully prepared launch of one (field, n, d) batch: kernel, grid and the
 // argument block (kept alive by the owner, e.g. a graph plan).
 struct LaunchSpec {
+  const Variant* variant = nullptr;
   const void* fn = nullptr;
   unsigned grid = 0, block = 0, shmem = 0;
   bool generic = false;  // runtime-n kernel (takes N as a second argument)
@@ -57,6 +60,10 @@ bool is_prime_u32(uint32_t n);
 int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
             void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec);
 int enqueue(LaunchSpec& spec, hipStream_t stream);
+// lane-group launches: points per block for LDS bytes per point `per`, the
+// one that keeps the most points resident per CU
+int wide_points_per_block(const Variant& v, size_t per);
+int max_lds_per_block();
 // argument checks of one bg_group (field, ranges, prime, pointers)
 int validate_group(const bg_group& g);
 
@@ -115,8 +122,11 @@ unsigned wide_lds_bytes(int N) {
 #define BG_REGISTER_WIDE(FIELDTAG, FLD, DMAX_, G_, PAD_, LC_)                                               \
   namespace bg {                                                                                            \
   template __global__ void bg_wide_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>(LaunchArgs, int);         \
+  template __global__ void bg_wide_queue_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>(                    \
+      const QueueGroup*, int, uint32_t, uint32_t*);                                                         \
   static Registrar BG_CAT(reg_, __COUNTER__)(Variant{                                                       \
       FIELDTAG, 0, DMAX_, G_ * LC_, 0, true, true, 1,                                                       \
       reinterpret_cast<const void*>(&bg_wide_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>),               \
-      &wide_lds_bytes<WideLayout<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>>, PAD_, LC_});                     \
+      &wide_lds_bytes<WideLayout<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>>, PAD_, LC_, nullptr,              \
+      reinterpret_cast<const void*>(&bg_wide_queue_kernel<FLD<DMAX_ / LC_, LC_>, DMAX_, G_, PAD_>)});       \
   }

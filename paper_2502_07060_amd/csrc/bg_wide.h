@@ -542,19 +542,13 @@ struct WideRecursion {
   }
 };
 
-// G items per point, each on LC = Fld::kL adjacent lanes (G LC divides 64),
-// blockDim.x / (G LC) points per block, LDS from the host (points per block x
-// WideLayout::offsets(N).total bytes).
+// One point of a lane-group launch: the G LC lanes of point slot pb of the
+// block (lane t of the point) compute point q0 of the launch described by a,
+// with the point's tables at lds + pb * WideLayout::offsets(N).total.
 template <class Fld, int DMAX, int G, bool PAD>
-__global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
-  extern __shared__ __align__(16) char lds[];
+__device__ __forceinline__ void wide_point(const LaunchArgs& a, int N, char* lds, int pb, int t, int64_t q0) {
   using Lay = WideLayout<Fld, DMAX, G, PAD>;
   using WR = WideRecursion<Fld, DMAX, G, PAD>;
-  constexpr int GL = G * WR::LC;  // lanes per point
-  static_assert(G >= 16 && 64 % GL == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
-  const int t = (int)(threadIdx.x % GL);
-  const int pb = (int)(threadIdx.x / GL);
-  const int64_t q0 = (int64_t)xcd_block_index() * (blockDim.x / GL) + pb;
   const bool valid = q0 < a.npts;
   const int64_t q = valid ? q0 : a.npts - 1;  // tail groups recompute the last point
   WR W(lds + (size_t)pb * Lay::offsets(N).total, N, t);
@@ -622,6 +616,57 @@ __global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
       }
       if (a.status && W.s == 0) a.status[q] = sing ? PT_SINGULAR : PT_OK;
     }
+  }
+}
+
+// G items per point, each on LC = Fld::kL adjacent lanes (G LC divides 64),
+// blockDim.x / (G LC) points per block, LDS from the host (points per block x
+// WideLayout::offsets(N).total bytes).
+template <class Fld, int DMAX, int G, bool PAD>
+__global__ __launch_bounds__(256) void bg_wide_kernel(LaunchArgs a, int N) {
+  extern __shared__ __align__(16) char lds[];
+  constexpr int GL = G * Fld::kL;  // lanes per point
+  static_assert(G >= 16 && 64 % GL == 0, "a lane group lies in one wavefront and owns up to 13 ranges");
+  const int t = (int)(threadIdx.x % GL);
+  const int pb = (int)(threadIdx.x / GL);
+  const int64_t q0 = (int64_t)xcd_block_index() * (blockDim.x / GL) + pb;
+  wide_point<Fld, DMAX, G, PAD>(a, N, lds, pb, t, q0);
+}
+
+// ---------------------------------------------------------------------------
+// persistent form over a work queue (batched launches, paper Sec. 3.2: the
+// per-launch offset that a fixed set of precompiled kernels removes)
+// ---------------------------------------------------------------------------
+// The blocks stay resident and take tiles from the queue with one atomic
+// increment each until it is empty; the group table is ordered by cost per
+// point, longest first, so the expensive groups start first and the cheap
+// ones fill the tail.  Every block reaches the exit: once the counter has
+// passed ntiles every further increment returns a value >= ntiles.
+template <class Fld, int DMAX, int G, bool PAD>
+__global__ __launch_bounds__(256) void bg_wide_queue_kernel(const QueueGroup* groups, int ngroups, uint32_t ntiles,
+                                                           uint32_t* next) {
+  // the first 16 bytes of the block's LDS hold the current tile, the points'
+  // tables follow (the host sizes the launch with kQueueLdsHeader included)
+  extern __shared__ __align__(16) char lds[];
+  uint32_t& tile_s = *reinterpret_cast<uint32_t*>(lds);
+  constexpr int GL = G * Fld::kL;
+  const int t = (int)(threadIdx.x % GL);
+  const int pb = (int)(threadIdx.x / GL);
+  const int P = (int)(blockDim.x / GL);
+  for (;;) {
+    if (threadIdx.x == 0) tile_s = atomicAdd(next, 1u);
+    __syncthreads();
+    // the same value in every thread of the block: kept in scalar registers,
+    // so the group lookup and its arguments are scalar loads
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(tile_s);
+    if (tile >= ntiles) return;
+    int g = 0;
+    while (g + 1 < ngroups && groups[g + 1].first_tile <= tile) ++g;
+    const LaunchArgs a = groups[g].args;
+    const int N = groups[g].N;
+    const int64_t q0 = (int64_t)(tile - groups[g].first_tile) * P + pb;
+    wide_point<Fld, DMAX, G, PAD>(a, N, lds + kQueueLdsHeader, pb, t, q0);
+    __syncthreads();  // tile_s and the LDS tables are reused by the next tile
   }
 }
 

@@ -292,3 +292,20 @@ def test_failed_autotune_keeps_the_previous_pin():
         assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == default
     finally:
         bg.bg_select_variant(field, n, d, -1)
+
+
+def _bad_batch():
+    g = bg.bg_group(bg.BG_FIELD_FP, 8, 6, 2147483631, 10, 10, DUMMY.value, DUMMY.value, DUMMY.value, None)
+    return (bg.bg_group * 1)(g)
+
+
+def test_batch_entry_points_validate_on_the_host():
+    """The batched calls check flags and every group before any device work."""
+    L = bg.lib()
+    arr = _bad_batch()
+    p = ctypes.cast(arr, ctypes.c_void_p)
+    assert L.bg_batch_run_ex(p, 1, 2, NULL) == bg.BG_EINVAL          # unknown flag
+    assert L.bg_batch_run_ex(p, 1, bg.BG_BATCH_QUEUE, NULL) == bg.BG_ENOTPRIME
+    plan = ctypes.c_void_p()
+    assert L.bg_batch_plan_create_ex(p, 1, 4, ctypes.byref(plan)) == bg.BG_EINVAL
+    assert not plan.value

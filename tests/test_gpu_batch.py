@@ -2,7 +2,8 @@
 group, exactly what the single-group entry points give (same kernels, so
 bit-identical in both fields), and the oracle's values; recorded plans
 (hipGraph) give the same on every replay; an invalid group rejects the
-whole batch before anything runs."""
+whole batch before anything runs.  The queue form (persistent lane-group
+launches over a device work queue) is held to the same bar."""
 import numpy as np
 import pytest
 
@@ -20,10 +21,16 @@ SHAPES = [("fp", 4, 4, 300), ("fp", 8, 6, 700), ("fp", 11, 8, 40), ("fp", 14, 10
           ("fp", 6, 5, 0), ("c128", 7, 8, 130)]
 
 
-def make_groups(torch_dev):
+# lane-group (runtime-n) groups of several tiles each, two of them sharing a
+# kernel variant (one persistent launch serves both), mixed with register ones
+QSHAPES = [("fp", 12, 8, 150), ("fp", 13, 8, 61), ("c128", 12, 6, 90), ("c128", 14, 4, 37),
+           ("fp", 8, 6, 700), ("c128", 8, 4, 300), ("fp", 14, 10, 9), ("c128", 5, 4, 0)]
+
+
+def make_groups(torch_dev, shapes=SHAPES):
     torch, dev = torch_dev
     groups, data = [], []
-    for t, (field, n, d, m) in enumerate(SHAPES):
+    for t, (field, n, d, m) in enumerate(shapes):
         g = dict(field=field, n=n, d=d, npts=m, seed=900 + t)
         k, e = I.group_inputs(g) if m else (np.zeros((0, n, d), np.uint32 if field == "fp" else complex),) * 2
         if field == "fp":
@@ -95,6 +102,39 @@ def test_plan_replays(torch_dev):
         plan.close()
 
 
+def test_queue_form_matches_single_calls_and_oracle(torch_dev):
+    groups, data = make_groups(torch_dev, QSHAPES)
+    bg.bg_batch_run_ex(groups, bg.BG_BATCH_QUEUE)
+    check_against_single_and_oracle(torch_dev, data, with_oracle=True)
+    # and the small shapes (one lane-group group per variant, few points)
+    groups, data = make_groups(torch_dev)
+    bg.bg_batch_run_ex(groups, bg.BG_BATCH_QUEUE)
+    check_against_single_and_oracle(torch_dev, data, with_oracle=False)
+
+
+def test_queue_plan_replays(torch_dev):
+    torch, _ = torch_dev
+    groups, data = make_groups(torch_dev, QSHAPES)
+    plan = bg.BatchPlan(groups, bg.BG_BATCH_QUEUE)
+    try:
+        for rep in range(3):
+            for x in data:                  # eager work between replays: poison the outputs
+                x["out"].fill_(-1 if x["field"] == "fp" else complex(7, 7))
+                x["st"].fill_(9)
+            torch.cuda.synchronize()
+            plan.launch()
+            check_against_single_and_oracle(torch_dev, data, with_oracle=False)
+    finally:
+        plan.close()
+
+
+def test_queue_form_rejects_unknown_flags(torch_dev):
+    groups, _ = make_groups(torch_dev)
+    with pytest.raises(bg.BGError) as ei:
+        bg.bg_batch_run_ex(groups, 2)
+    assert ei.value.code == bg.BG_EINVAL
+
+
 def test_invalid_group_rejects_whole_batch(torch_dev):
     torch, _ = torch_dev
     groups, data = make_groups(torch_dev)
@@ -109,10 +149,12 @@ def test_invalid_group_rejects_whole_batch(torch_dev):
     bg.bg_batch_run([])                        # empty batch is fine
 
 
-def test_full_batched_workload_sampled(torch_dev):
+@pytest.mark.parametrize("flags", [0, bg.BG_BATCH_QUEUE])
+def test_full_batched_workload_sampled(torch_dev, flags):
     """The measured batched workload itself (88 groups, 4*10^6 points, the
-    bench's launch configuration after autotuning): two sampled points per
-    group against the oracle, and no status other than OK."""
+    bench's launch configuration after autotuning), as a graph of per-group
+    launches and in the queue form: two sampled points per group against the
+    oracle, and no status other than OK."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
 
@@ -137,7 +179,7 @@ def test_full_batched_workload_sampled(torch_dev):
         st = torch.full((g["npts"],), 9, dtype=torch.uint8, device=dev)
         descs.append(bg.make_group(tk, te, out, st, p=P))
         keep.append((g, ks, es, out, st, tk, te))  # the descriptors hold raw pointers only
-    plan = bg.BatchPlan(descs)
+    plan = bg.BatchPlan(descs, flags)
     try:
         plan.launch()
         torch.cuda.synchronize()
