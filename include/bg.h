@@ -340,6 +340,20 @@ int bg_batch_run(const bg_group* groups, int ngroups, void* hip_stream);
 #define BG_BATCH_QUEUE 1
 int bg_batch_run_ex(const bg_group* groups, int ngroups, int flags, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bg_batch_run_ex with
+ * BG_BATCH_QUEUE, but the queue lives in a fixed device array of the library
+ * (256 KiB per GPU, held until the process ends; enough for about 1500
+ * lane-group groups per call) and every launch goes to hip_stream in turn,
+ * so the call allocates nothing, creates no streams and calls no allocating
+ * routine.  The array keeps the previous call's contents; each call rewrites
+ * the tables and zeroes the counters before its launches.  Calls that overlap
+ * on one GPU (concurrent streams or host threads) race on the array and must
+ * be serialised by the caller.  BG_ENOMEM if the call's queue does not fit the
+ * array; otherwise as bg_batch_run_ex.
+ */
+int bg_batch_run_noalloc(const bg_group* groups, int ngroups, void* hip_stream);
 
 /*
  * A batch plan records the launches of a fixed set of groups (pointers and

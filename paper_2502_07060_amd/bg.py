@@ -82,6 +82,7 @@ _SIGNATURES = {
     "bg_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bg_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_run_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "bg_batch_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "bg_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -579,6 +580,13 @@ def bg_batch_run_ex(groups, flags=0, stream=None) -> None:
     rc = lib().bg_batch_run_ex(ctypes.cast(arr, ctypes.c_void_p), len(groups), int(flags), _stream_ptr(stream))
     if rc != BG_OK:
         raise BGError(rc, "bg_batch_run_ex")
+
+
+def bg_batch_run_noalloc(groups, stream=None) -> None:
+    arr = _group_array(groups)
+    rc = lib().bg_batch_run_noalloc(ctypes.cast(arr, ctypes.c_void_p), len(groups), _stream_ptr(stream))
+    if rc != BG_OK:
+        raise BGError(rc, "bg_batch_run_noalloc")
 
 
 class BatchPlan:

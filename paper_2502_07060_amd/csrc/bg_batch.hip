@@ -9,7 +9,8 @@
 // longest tiles go first.  Register-kernel groups launch as before.  The
 // queue needs device memory beyond the inputs and outputs (one counter per
 // persistent launch and the table of its groups): bg_batch_run_ex allocates
-// it stream-ordered for the call, a plan at creation.
+// it stream-ordered for the call, a plan at creation, and
+// bg_batch_run_noalloc uses a fixed device array of the library instead.
 //
 // Every group runs the kernel variant selected for its (field, n, d) (the
 // autotuner's pin, else the default).  Groups are ordered longest first by
@@ -301,6 +302,30 @@ int run_units(std::vector<Unit>& units, QueuePlan& qp, unsigned char* buf, hipSt
   return rc;
 }
 
+// ---- the fixed device array of bg_batch_run_noalloc ------------------------
+// Counters and group tables of one call; each GPU the library runs on holds
+// its own copy until the process ends.  Host code must not use the array's
+// name as an address: its device address comes from hipGetSymbolAddress,
+// once per device.
+constexpr size_t kQueueScratchBytes = 256 * 1024;
+__device__ __align__(256) unsigned char scratch[kQueueScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char*> g_scratch_ptr;  // per device, null until resolved
+
+unsigned char* scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace bg
 
@@ -338,6 +363,24 @@ int bg_batch_run_ex(const bg_group* groups, int ngroups, int flags, void* hip_st
   std::vector<bg::Unit> units = bg::units_of(qp);
   if (rc == BG_OK) rc = bg::run_units(units, qp, buf, caller);
   if (buf && hipFreeAsync(buf, caller) != hipSuccess && rc == BG_OK) rc = BG_EHIP;
+  return rc;
+}
+
+int bg_batch_run_noalloc(const bg_group* groups, int ngroups, void* hip_stream) {
+  bg::QueuePlan qp;
+  int rc = bg::plan_queue(groups, ngroups, qp);
+  if (rc != BG_OK) return rc;
+  if (qp.bytes > bg::kQueueScratchBytes) return BG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  unsigned char* buf = nullptr;
+  if (qp.bytes) {
+    buf = bg::scratch_ptr();
+    if (!buf) return BG_EHIP;
+    rc = bg::stage_queue(qp, buf, st);
+  }
+  // everything on the caller's stream (no internal streams to create)
+  std::vector<bg::Unit> units = bg::units_of(qp);
+  for (size_t i = 0; rc == BG_OK && i < units.size(); ++i) rc = bg::launch_unit(units[i], qp, buf, st);
   return rc;
 }
 

@@ -300,12 +300,16 @@ def _bad_batch():
 
 
 def test_batch_entry_points_validate_on_the_host():
-    """The batched calls check flags and every group before any device work."""
+    """The batched calls check flags and every group before any device work
+    (the allocation-free one included)."""
     L = bg.lib()
     arr = _bad_batch()
     p = ctypes.cast(arr, ctypes.c_void_p)
     assert L.bg_batch_run_ex(p, 1, 2, NULL) == bg.BG_EINVAL          # unknown flag
     assert L.bg_batch_run_ex(p, 1, bg.BG_BATCH_QUEUE, NULL) == bg.BG_ENOTPRIME
+    assert L.bg_batch_run_noalloc(p, 1, NULL) == bg.BG_ENOTPRIME
+    assert L.bg_batch_run_noalloc(p, -1, NULL) == bg.BG_EINVAL
+    assert L.bg_batch_run_noalloc(NULL, 1, NULL) == bg.BG_EINVAL
     plan = ctypes.c_void_p()
     assert L.bg_batch_plan_create_ex(p, 1, 4, ctypes.byref(plan)) == bg.BG_EINVAL
     assert not plan.value
