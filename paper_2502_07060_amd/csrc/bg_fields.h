@@ -264,6 +264,14 @@ __device__ __forceinline__ cplx cmad(cplx a, cplx b, cplx acc) {
   return acc;
 }
 
+// Every complex vector is held with its time component multiplied by i (the
+// loaders apply it; it is exact: the two parts swap and one changes sign).
+// For x~ = (i x^0, x^1, ..., x^{d-1}) the plain sum of component products is
+// sum_mu x~_mu y~_mu = -x^0 y^0 + sum_k x^k y^k = -(x.y), and the map is
+// linear, so currents built from such vectors carry it too.  Dot products
+// are then plain sums and "priming" the time component is the identity: no
+// multiplication by a time sign in any dot product.  Root currents written
+// to memory are mapped back (component 0 times -i).
 template <int DL, int L>
 struct C128Field {
   static constexpr int kDL = DL, kL = L;
@@ -271,14 +279,10 @@ struct C128Field {
   using S = cplx;
   using A = cplx;
   static constexpr bool exact = false;
-  double time_sign;  // -1 on the lane holding mu = 0 (slot 0), +1 elsewhere
 
-  __device__ C128Field(int s) : time_sign((L == 1 || s == 0) ? -1.0 : 1.0) {}
+  __device__ C128Field(int) {}
 
-  __device__ __forceinline__ E prime0(E x) const {
-    if constexpr (L == 1) return cneg(x);
-    else return {x.re * time_sign, x.im * time_sign};
-  }
+  __device__ __forceinline__ E prime0(E x) const { return x; }
   __device__ __forceinline__ E esub(E a, E b) const { return csub(a, b); }
   __device__ __forceinline__ E eadd(E a, E b) const { return cadd(a, b); }
   __device__ __forceinline__ S sneg(S a) const { return cneg(a); }
@@ -304,7 +308,7 @@ struct C128Field {
   }
   template <bool LAZY = false>
   __device__ __forceinline__ S ndot_u(const E* x, const E* y) const {
-    cplx t = cmul(prime0(x[0]), y[0]);
+    cplx t = cmul(x[0], y[0]);
 #pragma unroll
     for (int c = 1; c < DL; ++c) t = cmad(x[c], y[c], t);
     return finish_dot(t);

@@ -335,9 +335,11 @@ __global__ __launch_bounds__(256) void bg_generic_kernel(LaunchArgs a, int N) {
 #pragma unroll
         for (int c = 0; c < DMAX; ++c) {
           if (c < a.d) {
+            // component 0 back from its factor i: K^0 = -i (i K^0)
+            const cplx k = c == 0 ? cplx{kroot[c].im, -kroot[c].re} : kroot[c];
             double2 o;
-            o.x = singular ? __builtin_nan("") : 2.0 * kroot[c].re;
-            o.y = singular ? __builtin_nan("") : 2.0 * kroot[c].im;
+            o.x = singular ? __builtin_nan("") : 2.0 * k.re;
+            o.y = singular ? __builtin_nan("") : 2.0 * k.im;
             static_cast<double2*>(a.cur)[(int64_t)c * a.ld + q] = o;
           }
         }

@@ -129,15 +129,13 @@ struct Loader<C128Field<DL, L>> {
     const double2 v =
         static_cast<const double2*>(base)[((int64_t)l * a.d + (in ? mu : 0)) * a.ld + q];
     // selects, not branches: an early return here lets the compiler sink each
-    // load into a block of its own, which serialises the point's loads
+    // load into a block of its own, which serialises the point's loads.
+    // Component 0 is multiplied by i (C128Field holds time components that
+    // way), and with ALT so are components 2, 4, 6, ...
     double re = in ? v.x : 0.0, im = in ? v.y : 0.0;
-    if constexpr (ALT) {
-      const bool rot = mu >= 2 && (mu & 1) == 0;  // times i, exactly
-      const double r2 = rot ? -im : re, i2 = rot ? re : im;
-      re = r2;
-      im = i2;
-    }
-    return cplx{re, im};
+    const bool rot = mu == 0 || (ALT && mu >= 2 && (mu & 1) == 0);  // times i, exactly
+    const double r2 = rot ? -im : re, i2 = rot ? re : im;
+    return cplx{r2, i2};
   }
   __device__ static cplx get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                                 uint32_t& maxraw) {
@@ -651,9 +649,11 @@ void bg_recursion_kernel(LaunchArgs a) {
         for (int c = 0; c < DL; ++c) {
           const int mu = s * DL + c;
           if (mu < a.d) {
+            // component 0 back from its factor i: K^0 = -i (i K^0)
+            const cplx k = mu == 0 ? cplx{kroot[c].im, -kroot[c].re} : kroot[c];
             double2 o;
-            o.x = singular ? __builtin_nan("") : 2.0 * kroot[c].re;
-            o.y = singular ? __builtin_nan("") : 2.0 * kroot[c].im;
+            o.x = singular ? __builtin_nan("") : 2.0 * k.re;
+            o.y = singular ? __builtin_nan("") : 2.0 * k.im;
             static_cast<double2*>(a.cur)[(int64_t)mu * a.ld + q] = o;
           }
         }

@@ -598,8 +598,10 @@ __device__ __forceinline__ void wide_point(const LaunchArgs& a, int N, char* lds
           const int mu = W.co + c;
           if (mu < a.d) {
             double2 o;
-            o.x = sing ? __builtin_nan("") : 2.0 * kroot[c].re;
-            o.y = sing ? __builtin_nan("") : 2.0 * kroot[c].im;
+            // component 0 back from its factor i: K^0 = -i (i K^0)
+            const cplx k = mu == 0 ? cplx{kroot[c].im, -kroot[c].re} : kroot[c];
+            o.x = sing ? __builtin_nan("") : 2.0 * k.re;
+            o.y = sing ? __builtin_nan("") : 2.0 * k.im;
             static_cast<double2*>(a.cur)[(int64_t)mu * a.ld + q] = o;
           }
         }
