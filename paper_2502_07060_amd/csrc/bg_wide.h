@@ -13,9 +13,9 @@
 //   J_B with the stored -D/2 of the other part (see bg_kernel.h),
 //
 // each item summing its contribution to K'(S) over the full d components in
-// one lane (no cross-lane dot products).  With G < 32 the cuts c and
-// i + j - 1 - c form one item, which evens out the number of four-gluon
-// splits per item.  Items are dealt to the lanes in rounds of G; after each
+// one lane (no cross-lane dot products).  With G = 16 (and with G = 32 where
+// the launch asks for it, at n = 14) the cuts c and i + j - 1 - c form one
+// item, which evens out the number of four-gluon splits per item.  Items are dealt to the lanes in rounds of G; after each
 // round the lane that owns S (lane i) adds the round's partial sums of S, in
 // cut order, to its accumulator, so the result does not depend on timing.
 // The owner then finishes S: J(S) = 2 K'(S) / P_S^2 into the LDS table, or
@@ -107,7 +107,12 @@ struct WideRecursion {
   static constexpr int LC = Fld::kL;    // lanes per work item
   using Rec = Recursion<Fld, 2, DL, LC>;  // scalar helpers
   static constexpr bool kFp = Fld::exact;
-  static constexpr bool kPairs = G < 32;
+  // With 16 items per point an item always takes a pair of cuts; with 32 the
+  // launch chooses (LaunchArgs::wide_pairs): pairs keep every length of
+  // n = 14 within one round of 32 items, single cuts are more items of
+  // shorter four-gluon loops; with 64, single cuts
+  static constexpr bool kPairsAlways = G < 32;
+  static constexpr bool kPairsMaybe = G <= 32;
 
   E* Jt;
   E* Mt;
@@ -408,9 +413,10 @@ struct WideRecursion {
       if (g < N) loadM(g, Pown);
     }
 
+    const bool pairs = kPairsAlways || (kPairsMaybe && a.wide_pairs != 0);
     for (int m = 2; m <= N; ++m) {
       const int nr = N - m + 1;                 // ranges of length m: i = 0 .. nr-1
-      const int per = kPairs ? m / 2 : m - 1;   // items per range
+      const int per = pairs ? m / 2 : m - 1;    // items per range
       const int items = nr * per;
       const bool own = g < nr;
       const int oi = g, oj = g + m - 1;         // the range this lane owns
@@ -427,16 +433,16 @@ struct WideRecursion {
           A Kp[DL];
 #pragma unroll
           for (int c = 0; c < DL; ++c) Kp[c] = F.azero();
-          const int c1 = i + u, c2 = kPairs ? j - 1 - u : c1;
+          const int c1 = i + u, c2 = pairs ? j - 1 - u : c1;
           if constexpr (kFp) {
             int64_t nDs = 0;
             cut3(F, i, j, c1, Pp, Pp, Pp, Kp, nDs);
-            if (kPairs && c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
+            if (pairs && c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
             cut4(F, i, j, c1, c2, Kp);
             pscal[g] = fp_redc2(fp_fold(nDs, F.k), F.k);  // -(sum of J_A.J_B) / 2
           } else {
             S nDs = F.szero();
-            if constexpr (kPairs) {
+            if (pairs) {
               E PA1[DL], PB1[DL], PA2[DL], PB2[DL];
               pair_momenta(i, j, c1, c2, PA1, PB1, PA2, PB2);
               cut3(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
