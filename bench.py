@@ -40,13 +40,18 @@ INT_MAD_PEAK_TOPS = LANE_SLOTS_PER_S / 1e12
 
 
 def kernel_source_digest() -> str:
+    """Hash of what decides the recursion kernels' code and launch shape: the
+    kernel headers, the launch layer (bg_api.hip) and the build script that
+    instantiates them with its compiler flags."""
     import hashlib
-    csrc = os.path.join(ROOT, "paper_2502_07060_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_2502_07060_amd")
+    csrc = os.path.join(pkg, "csrc")
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc)) if f.endswith(".h")]
+    files += [os.path.join(csrc, "bg_api.hip"), os.path.join(pkg, "build.py")]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -473,11 +473,13 @@ int bg_select_variant(int field, int n, int d, int index);
 /*
  * bg_autotune -- times every variant compiled for (field, n, d) on npts
  * synthetic points (uniform residues mod p, or complex values with parts in
- * [-1, 1)), reps launches each after one warm-up, on hip_stream; pins the
- * fastest and returns its index (>= 0) or a negative error code.  ms_out
- * (may be NULL) receives the time per launch of each variant in bg_variants
- * order, up to cap entries.  Allocates and frees its own device buffers; it
- * synchronises the stream.  p is ignored for the complex field.
+ * [-1, 1)), reps launches each after one warm-up, on hip_stream; the variants
+ * within 5 % of the fastest are timed three more times, in turns, each keeping
+ * its best time.  Pins the fastest and returns its index (>= 0) or a negative
+ * error code.  ms_out (may be NULL) receives the time per launch of each
+ * variant in bg_variants order, up to cap entries.  Allocates and frees its
+ * own device buffers; it synchronises the stream.  p is ignored for the
+ * complex field.
  */
 int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps,
                 double* ms_out, int cap, void* hip_stream);

@@ -211,7 +211,7 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.d = d;
   a.fp = fp;
   a.metric = BG_METRIC_MOSTLY_MINUS;
-  a.ialt = 0;
+  a.ialt = fp.one;  // the mostly-minus factor; launch() sets i R for the alternating metric
   a.cur = nullptr;
   // lane-group kernels with 32 items per point (L = 32 LC lanes): pairs of
   // cuts at n = 14, where every length then fits one round of items
@@ -283,7 +283,7 @@ int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* moment
   const int rc = prepare(field, n, d, npts, ld, momenta, pols, out, status, fp, spec);
   if (rc != BG_OK) return rc;
   spec.args.metric = metric;
-  spec.args.ialt = (metric == BG_METRIC_ALTERNATING && field == FIELD_FP) ? fp_sqrt_minus_one_mont((uint32_t)fp.p) : 0;
+  if (metric == BG_METRIC_ALTERNATING && field == FIELD_FP) spec.args.ialt = fp_sqrt_minus_one_mont((uint32_t)fp.p);
   return enqueue(spec, stream);
 }
 

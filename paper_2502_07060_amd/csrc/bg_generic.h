@@ -92,8 +92,8 @@ struct GenericRecursion {
       E k[DMAX], e[DMAX];
 #pragma unroll
       for (int c = 0; c < DMAX; ++c) {
-        k[c] = Loader<Fld>::get_rt(a, a.momenta, l, c, q, bad);
-        e[c] = Loader<Fld>::get_rt(a, a.pols, l, c, q, bad);
+        k[c] = Loader<Fld>::template get<MetricRT>(a, a.momenta, l, c, q, bad);
+        e[c] = Loader<Fld>::template get<MetricRT>(a, a.pols, l, c, q, bad);
         J(range_idx(N, l, l), c) = e[c];
       }
       k[0] = F.prime0(k[0]);
@@ -109,7 +109,7 @@ struct GenericRecursion {
     }
     E epsn[DMAX];
 #pragma unroll
-    for (int c = 0; c < DMAX; ++c) epsn[c] = Loader<Fld>::get_rt(a, a.pols, N, c, q, bad);
+    for (int c = 0; c < DMAX; ++c) epsn[c] = Loader<Fld>::template get<MetricRT>(a, a.pols, N, c, q, bad);
 
     // F_p propagator inverses: prefix products in iv(), y recomputed backwards
     if constexpr (kFp) {

@@ -59,7 +59,8 @@ struct LaunchArgs {
   // metric: 0 mostly-minus; 1 alternating diag(1, -1, 1, -1, ...), mapped onto
   // the mostly-minus one on load (see Loader)
   int metric;
-  int32_t ialt;  // F_p, alternating metric: a square root of -1 times R (Montgomery form)
+  int32_t ialt;  // F_p: factor of the components 2, 4, ... at load: a square root of -1 times R
+                 // in the alternating metric, R (Montgomery one) in the mostly-minus one
   // root-current mode: when non-null, the kernels write K([1..n-1]) (d
   // components, [d][ld]) here instead of M to `out`
   void* cur;
@@ -92,15 +93,26 @@ constexpr unsigned kQueueLdsHeader = 16;  // LDS bytes before the points' tables
 // ((i x^mu)(i y^mu) (-1) = +x^mu y^mu), and the amplitude is built from such
 // products alone, so the loaders apply the map and every kernel runs
 // unchanged.  Exact in both fields: over C it swaps and negates parts, over
-// F_p it is one Montgomery product with i R.  ALT is a compile-time switch so
-// that the mostly-minus loads carry no trace of it (the register kernel
-// branches once, at its entry, between two instantiations of its body).
+// F_p it is one Montgomery product with i R.
+//
+// M says where the metric comes from: MetricMM / MetricAlt fix it at compile
+// time, MetricRT reads a.metric.  The F_p register kernel branches once, at
+// its entry, between a MetricMM and a MetricAlt body: its mostly-minus body
+// compiles to faster code that way than a single body with the map chosen at
+// run time (0.48 against 0.51 ms per 2^20 points at n = 8, d = 6), although
+// the compiler then waits for each load of the alternating body before
+// issuing the next, which makes that metric about twice as slow.  The complex
+// register kernel and the runtime-n kernels take MetricRT: one body, where
+// the map is a select (complex) or a product with a.ialt, which is R in the
+// mostly-minus metric (F_p).
+enum : int { MetricMM = 0, MetricAlt = 1, MetricRT = 2 };
+
 template <class Fld>
 struct Loader;
 
 template <int DL, int L, bool SC>
 struct Loader<FpField<DL, L, SC>> {
-  template <bool ALT = false>
+  template <int M>
   __device__ static int32_t get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                                 uint32_t& maxraw) {
     const bool in = mu < a.d;
@@ -109,23 +121,24 @@ struct Loader<FpField<DL, L, SC>> {
     const uint32_t xi = in ? x : 0u;
     maxraw = maxraw > xi ? maxraw : xi;
     const uint32_t xc = xi < (uint32_t)a.fp.p ? xi : 0u;
-    int32_t v = fp_from_canonical(xc, a.fp);
-    if constexpr (ALT) {  // a select, so that the loads stay in one block
-      const int32_t w = fp_mul(v, a.ialt, a.fp);
-      v = (mu >= 2 && (mu & 1) == 0) ? w : v;
+    const bool rot = mu >= 2 && (mu & 1) == 0;
+    if constexpr (M == MetricRT) {
+      // both balanced: the product with R is the conversion, bit for bit
+      return rot ? fp_mul((int32_t)xc, a.ialt, a.fp) : fp_from_canonical(xc, a.fp);
+    } else {
+      int32_t v = fp_from_canonical(xc, a.fp);
+      if constexpr (M == MetricAlt) {  // a select, so that the loads stay in one block
+        const int32_t w = fp_mul(v, a.ialt, a.fp);
+        v = rot ? w : v;
+      }
+      return v;
     }
-    return v;
-  }
-  // the metric chosen at run time (lane-group and one-point-per-lane kernels)
-  __device__ static int32_t get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
-                                   uint32_t& maxraw) {
-    return a.metric != 0 ? get<true>(a, base, l, mu, q, maxraw) : get<false>(a, base, l, mu, q, maxraw);
   }
 };
 
 template <int DL, int L>
 struct Loader<C128Field<DL, L>> {
-  template <bool ALT = false>
+  template <int M>
   __device__ static cplx get(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
                              uint32_t&) {
     const bool in = mu < a.d;
@@ -134,15 +147,12 @@ struct Loader<C128Field<DL, L>> {
     // selects, not branches: an early return here lets the compiler sink each
     // load into a block of its own, which serialises the point's loads.
     // Component 0 is multiplied by i (C128Field holds time components that
-    // way), and with ALT so are components 2, 4, 6, ...
+    // way), and in the alternating metric so are components 2, 4, 6, ...
+    const bool alt = M == MetricAlt || (M == MetricRT && a.metric != 0);
     double re = in ? v.x : 0.0, im = in ? v.y : 0.0;
-    const bool rot = mu == 0 || (ALT && mu >= 2 && (mu & 1) == 0);  // times i, exactly
+    const bool rot = mu == 0 || (alt && mu >= 2 && (mu & 1) == 0);  // times i, exactly
     const double r2 = rot ? -im : re, i2 = rot ? re : im;
     return cplx{r2, i2};
-  }
-  __device__ static cplx get_rt(const LaunchArgs& a, const void* base, int l, int mu, int64_t q,
-                                uint32_t& maxraw) {
-    return a.metric != 0 ? get<true>(a, base, l, mu, q, maxraw) : get<false>(a, base, l, mu, q, maxraw);
   }
 };
 
@@ -264,7 +274,7 @@ struct Recursion {
     }
   }
 
-  template <int BLOCK, bool ALT>
+  template <int BLOCK, int M>
   __device__ static void run(const Fld& F, const LaunchArgs& a, int64_t q, int s, uint32_t& bad,
                              bool& singular, S& result, E (&kroot)[DL], Lds<BLOCK>* lds) {
     constexpr bool kFp = Fld::exact;
@@ -302,8 +312,8 @@ struct Recursion {
       E k[DL];
 #pragma unroll
       for (int c = 0; c < DL; ++c) {
-        k[c] = Loader<Fld>::template get<ALT>(a, a.momenta, l, mu0 + c, q, bad);
-        J[R::idx(l, l)][c] = Loader<Fld>::template get<ALT>(a, a.pols, l, mu0 + c, q, bad);
+        k[c] = Loader<Fld>::template get<M>(a, a.momenta, l, mu0 + c, q, bad);
+        J[R::idx(l, l)][c] = Loader<Fld>::template get<M>(a, a.pols, l, mu0 + c, q, bad);
       }
       k[0] = F.prime0(k[0]);
       if constexpr (kFp) {
@@ -317,7 +327,7 @@ struct Recursion {
       }
     });
 #pragma unroll
-    for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::template get<ALT>(a, a.pols, N, mu0 + c, q, bad);
+    for (int c = 0; c < DL; ++c) epsn[c] = Loader<Fld>::template get<M>(a, a.pols, N, mu0 + c, q, bad);
 
     // ---- a3/a4 (F_p): all propagator denominators, one batched inversion -----
     if constexpr (kFp) {
@@ -604,8 +614,8 @@ void bg_recursion_kernel(LaunchArgs a) {
   typename Fld::E kroot[DL];
   if constexpr (Fld::exact) {
     Fld F(a.fp, s);
-    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, kroot, &lds);
-    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, kroot, &lds);
+    if (a.metric != 0) Rec::template run<BLOCK, MetricAlt>(F, a, q, s, bad, singular, res, kroot, &lds);
+    else Rec::template run<BLOCK, MetricMM>(F, a, q, s, bad, singular, res, kroot, &lds);
     if constexpr (L > 1)
       bad = group_sum<L>(bad, [](uint32_t x, uint32_t y) { return x > y ? x : y; },
                          [](auto ctrl, uint32_t v) { return dpp_u32<decltype(ctrl)::value>(v); });
@@ -644,8 +654,7 @@ void bg_recursion_kernel(LaunchArgs a) {
     }
   } else {
     Fld F(s);
-    if (a.metric != 0) Rec::template run<BLOCK, true>(F, a, q, s, bad, singular, res, kroot, &lds);
-    else Rec::template run<BLOCK, false>(F, a, q, s, bad, singular, res, kroot, &lds);
+    Rec::template run<BLOCK, MetricRT>(F, a, q, s, bad, singular, res, kroot, &lds);
     if (a.cur) {
       if (valid) {
 #pragma unroll

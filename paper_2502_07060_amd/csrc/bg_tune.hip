@@ -91,9 +91,9 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
     return bg_amplitudes_c128(n, d, npts, npts, (const double*)mom.p, (const double*)pol.p, (double*)out.p,
                               (uint8_t*)sta.p, st);
   };
-  int rc = BG_OK, best = -1;
-  double best_ms = 1e300;
-  for (int k = 0; k < count && rc == BG_OK; ++k) {
+  int rc = BG_OK;
+  // time of one launch of variant k, averaged over reps after a warm-up
+  auto time_variant = [&](int k, double& per) {
     bg_select_variant(field, n, d, vs[k].index);
     rc = run();  // warm-up
     float ms = 0.f;
@@ -102,10 +102,32 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
     if (rc == BG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
       rc = BG_EHIP;
-    const double per = rc == BG_OK ? (double)ms / reps : -1.0;
-    if (ms_out && k < cap) ms_out[k] = per;
-    if (rc == BG_OK && per < best_ms) {
-      best_ms = per;
+    per = rc == BG_OK ? (double)ms / reps : -1.0;
+  };
+  std::vector<double> per(count, 1e300);
+  for (int k = 0; k < count && rc == BG_OK; ++k) time_variant(k, per[k]);
+  // variants within 5 % of the fastest are timed again, in turns, three more
+  // times, each keeping its best: one pass cannot separate kernels that close
+  // (clocks and the order of the pass move single timings by a few percent)
+  if (rc == BG_OK) {
+    const double first = *std::min_element(per.begin(), per.end());
+    std::vector<int> close;
+    for (int k = 0; k < count; ++k)
+      if (per[k] <= 1.05 * first) close.push_back(k);
+    for (int round = 0; round < 3 && close.size() > 1 && rc == BG_OK; ++round)
+      for (int k : close) {
+        double t = 0.0;
+        time_variant(k, t);
+        if (rc != BG_OK) break;
+        per[k] = std::min(per[k], t);
+      }
+  }
+  int best = -1;
+  double best_ms = 1e300;
+  for (int k = 0; k < count && rc == BG_OK; ++k) {
+    if (ms_out && k < cap) ms_out[k] = per[k];
+    if (per[k] < best_ms) {
+      best_ms = per[k];
       best = vs[k].index;
     }
   }

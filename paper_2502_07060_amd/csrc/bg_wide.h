@@ -243,12 +243,12 @@ struct WideRecursion {
     for (int r = ln; r < rows; r += G * LC) {
       const int which = r / DMAX, c = r % DMAX;
       if (which <= N) {
-        const E e = Loader<Fld>::get_rt(a, a.pols, which, c, q, bad);
+        const E e = Loader<Fld>::template get<MetricRT>(a, a.pols, which, c, q, bad);
         if (which < N) Jat(rid(which, which), c) = e;
         else En[c] = e;
       } else {
         const int l = which - N - 1;
-        E k = Loader<Fld>::get_rt(a, a.momenta, l, c, q, bad);
+        E k = Loader<Fld>::template get<MetricRT>(a, a.momenta, l, c, q, bad);
         if constexpr (kFp) {
           Mat(l + 1, c) = k;  // raw k_l, summed below
         } else {
