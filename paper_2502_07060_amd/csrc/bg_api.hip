@@ -213,9 +213,6 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
   a.metric = BG_METRIC_MOSTLY_MINUS;
   a.ialt = fp.one;  // the mostly-minus factor; launch() sets i R for the alternating metric
   a.cur = nullptr;
-  // lane-group kernels with 32 items per point (L = 32 LC lanes): pairs of
-  // cuts at n = 14, where every length then fits one round of items
-  a.wide_pairs = (v->generic && v->L / v->split == 32 && n >= 14) ? 1 : 0;
   spec.variant = v;
   spec.fn = (field == FIELD_FP && v->fn_sc && fp_small_fold(fp)) ? v->fn_sc : v->fn;
   spec.generic = v->generic;

@@ -64,9 +64,6 @@ struct LaunchArgs {
   // root-current mode: when non-null, the kernels write K([1..n-1]) (d
   // components, [d][ld]) here instead of M to `out`
   void* cur;
-  // lane-group kernels with 32 work items per point: 1 when an item takes
-  // the pair of cuts c and i + j - 1 - c (as with 16 items), 0 for one cut
-  int wide_pairs;
 };
 
 // One group of a persistent queue launch (bg_wide_queue_kernel): its launch

@@ -1,45 +1,57 @@
-// Berends-Giele recursion for large n (paper Sec. 2.2) with a group of G
-// lanes per phase-space point and the point's current table shared in LDS.
+// Berends-Giele recursion for large n (paper Sec. 2.2) with a group of G work
+// items per phase-space point and the point's current table shared in LDS.
 //
 // One lane per point (bg_generic.h) needs the whole table per lane, so only a
-// handful of points fit a CU at n >= 9.  Here the G lanes of a group split the
+// handful of points fit a CU at n >= 9.  Here the G items of a group split the
 // work of one point instead.  Ranges of one length m depend only on shorter
-// ranges, so the recursion advances length by length; within a length, the
-// work items are (range S = [i..j], cut c) for i <= c < j:
+// ranges, so the recursion advances length by length.  Within a length, a
+// work item is (range S = [i..j], the pair of cuts c and i + j - 1 - c) for
+// i <= c < j (one cut when the two coincide):
 //
-//   the three-gluon split A = [i..c] | B = [c+1..j],
-//   every four-gluon split [i..c] | [c+1..t] | [t+1..j] (c < t < j),
+//   the three-gluon split A = [i..c] | B = [c+1..j] of each cut,
+//   every four-gluon split [i..c] | [c+1..t] | [t+1..j] (c < t < j) of each,
 //   the two adjacent-pair terms of the four-gluon vertex that pair J_A or
 //   J_B with the stored -D/2 of the other part (see bg_kernel.h),
 //
-// each item summing its contribution to K'(S) over the full d components in
-// one lane (no cross-lane dot products).  With G = 16 (and with G = 32 where
-// the launch asks for it, at n = 14) the cuts c and i + j - 1 - c form one
-// item, which evens out the number of four-gluon splits per item.  Items are dealt to the lanes in rounds of G; after each
-// round the lane that owns S (lane i) adds the round's partial sums of S, in
-// cut order, to its accumulator, so the result does not depend on timing.
-// The owner then finishes S: J(S) = 2 K'(S) / P_S^2 into the LDS table, or
-// at the root M = 2 eps_n . K'.
+// summing its contribution to K'(S) over the full d components in its lanes.
+// The pair evens out the four-gluon splits: every item of a length does the
+// same work (two cuts, m - 2 splits), so the lanes of a wave run the same
+// code.  A range's ceil((m - 1) / 2) items sit in a block of `per` item slots
+// (the next power of two), a round holds G / per ranges, and after each round
+// the items of a range add their sums with a butterfly across their lanes (a
+// fixed order that gives every lane the same value); the first item then
+// finishes S: J(S) = 2 K'(S) / P_S^2 into the LDS table, or at the root
+// M = 2 eps_n . K'.  One wave barrier per length; the result does not depend
+// on timing.
 //
-// Same identities as the register kernel; the sum over splits is taken in
-// item order instead of split order, which changes only the rounding of the
-// complex path.  F_p propagator inverses: each lane inverts its share of the
-// denominators with one batched inversion and one Fermat power.
+// Sub-range momenta.  F_p: exact prefix sums Q_l, P_S = Q_{j+1} - Q_i.
+// Complex: prefix sums of the primed momenta held as unevaluated sums hi + lo
+// (an error-free two-sum at every leg), and P_S = (hi_{j+1} - hi_i) +
+// (lo_{j+1} - lo_i): the difference of the high parts rounds once, relative
+// to P_S itself, so P_S is as accurate as a direct sum of its legs, where a
+// difference of plain prefix sums loses the digits by which the partial sums
+// exceed P_S.
 //
-// Component split (complex).  With Fld = C128Field<DL, LC>, LC > 1, each work
-// item belongs to LC adjacent lanes that hold DL = DMAX / LC components each
-// and sum dot products over DPP: LC times the lanes per point for the same
-// LDS footprint, which is what limits how many points a CU holds at large n.
+// Same identities as the register kernel; the sum over splits is taken in the
+// schedule's order, which changes only the rounding of the complex path.
+// F_p propagator inverses: each item inverts its share of the denominators
+// with one batched inversion and one Fermat power.
+//
+// Component split.  With Fld = C128Field<DL, LC> or FpField<DL, LC>, LC > 1,
+// each work item belongs to LC adjacent lanes that hold DL = DMAX / LC
+// components each and sum dot products over DPP: LC times the lanes per point
+// for the same LDS footprint, which is what limits how many points a CU holds
+// at large n.
 //
 // LDS access.  A lane reads whole table rows, with 16-byte reads (complex
 // elements are 16 bytes; F_p rows when they start on 16-byte boundaries).
 // The lanes of a wave read rows of unrelated ranges at once, so a row stride
 // that is a multiple of 64 bytes (complex d = 4 or 8) sends most of them to
 // the same banks; the padded layouts round a row up to an odd number of
-// 16-byte units.  Complex sub-range momenta are direct left-to-right sums of
-// the legs (no prefix differences); a pair item reads each leg of S once for
-// both of its cuts.
+// 16-byte units.
 #pragma once
+
+#include <type_traits>
 
 #include "bg_generic.h"
 
@@ -49,7 +61,6 @@ template <class Fld, int DMAX, int G, bool PAD>
 struct WideLayout {
   using E = typename Fld::E;
   using S = typename Fld::S;
-  using A = typename Fld::A;
   static constexpr bool kFp = Fld::exact;
   // row stride (elements) of the vector tables.  PAD makes a row an odd
   // number of 16-byte units (complex: an odd element count; F_p: 4 or 12
@@ -61,39 +72,60 @@ struct WideLayout {
   // table bases are 16-byte aligned)
   static constexpr bool kVec4 = kFp && kS % 4 == 0 && Fld::kDL % 4 == 0;
   struct Off {
-    unsigned J, mom, epsn, nDh, nc, inv, part, pscal, flags, total;
+    unsigned J, mom, epsn, nDh, nc, inv, flags, total;
   };
   __host__ __device__ static int ncur(int N) { return N * (N + 1) / 2 - 1; }
   __host__ __device__ static unsigned up16(size_t x) { return (unsigned)((x + 15) / 16 * 16); }
-  // per-point LDS offsets (bytes): current table [range][component], momenta
-  // (F_p: prefix sums Q_0..Q_N; complex: primed k'_0..k'_{N-1}) [leg][component],
-  // eps_n, scalars by range index, one partial K [lane][component] and one
-  // scalar per lane, flags.  A vector is contiguous, so a lane reads it with
-  // wide LDS loads.
+  // per-point LDS offsets (bytes): current table [range][component], prefix
+  // sums Q_0..Q_N [leg][component] (complex: the high parts, then the low
+  // parts), eps_n, scalars by range index, flags.  A vector is contiguous, so
+  // a lane reads it with wide LDS loads.
   __host__ __device__ static Off offsets(int N) {
     Off o{};
     unsigned x = 0;
     o.J = x;      x += up16((size_t)ncur(N) * kS * sizeof(E));
-    o.mom = x;    x += up16((size_t)(N + 1) * kS * sizeof(E));
+    o.mom = x;    x += up16((size_t)(kFp ? 1 : 2) * (N + 1) * kS * sizeof(E));
     o.epsn = x;   x += up16((size_t)DMAX * sizeof(E));
     o.nDh = x;    x += up16((size_t)ncur(N) * sizeof(S));
     o.nc = x;     x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
     o.inv = x;    x += kFp ? up16((size_t)ncur(N) * sizeof(S)) : 0u;
-    o.part = x;   x += up16((size_t)G * kS * sizeof(A));  // one row per item slot
-    o.pscal = x;  x += up16((size_t)G * sizeof(S));
     o.flags = x;  x += 16;
     o.total = x;
     return o;
   }
 };
 
-// The G lanes of a group lie in one wavefront (G divides 64), so a group needs
-// no workgroup barrier: waiting for this wave's LDS operations and keeping
-// the compiler from moving LDS accesses across the point is enough.
+// The G items of a group lie in one wavefront (G LC divides 64), so a group
+// needs no workgroup barrier: waiting for this wave's LDS operations and
+// keeping the compiler from moving LDS accesses across the point is enough.
 __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// the value of lane (this lane XOR ST): ds_swizzle in bit mode within 32
+// lanes, ds_bpermute across the halves of the wave
+template <int ST>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  static_assert(ST >= 1 && ST <= 32 && (ST & (ST - 1)) == 0, "a lane distance that is a power of two");
+  if constexpr (ST < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (ST << 10));
+  else return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ ST) << 2), (int)v);
+}
+template <int ST>
+__device__ __forceinline__ int64_t lane_xor(int64_t v) {
+  u32x2 p = __builtin_bit_cast(u32x2, v);
+  p.x = lane_xor<ST>(p.x);
+  p.y = lane_xor<ST>(p.y);
+  return __builtin_bit_cast(int64_t, p);
+}
+template <int ST>
+__device__ __forceinline__ double lane_xor(double v) {
+  return __builtin_bit_cast(double, lane_xor<ST>(__builtin_bit_cast(int64_t, v)));
+}
+template <int ST>
+__device__ __forceinline__ cplx lane_xor(cplx v) {
+  return cplx{lane_xor<ST>(v.re), lane_xor<ST>(v.im)};
 }
 
 template <class Fld, int DMAX, int G, bool PAD>
@@ -107,21 +139,17 @@ struct WideRecursion {
   static constexpr int LC = Fld::kL;    // lanes per work item
   using Rec = Recursion<Fld, 2, DL, LC>;  // scalar helpers
   static constexpr bool kFp = Fld::exact;
-  // With 16 items per point an item always takes a pair of cuts; with 32 the
-  // launch chooses (LaunchArgs::wide_pairs): pairs keep every length of
-  // n = 14 within one round of 32 items, single cuts are more items of
-  // shorter four-gluon loops; with 64, single cuts
-  static constexpr bool kPairsAlways = G < 32;
-  static constexpr bool kPairsMaybe = G <= 32;
+  // per-item sum of the -(J_A . J_B) of its cuts: F_p an int64 sum of
+  // products with 1/2, complex the plain sum
+  using NDS = std::conditional_t<kFp, int64_t, S>;
 
   E* Jt;
   E* Mt;
+  E* Ml;
   E* En;
   S* nDht;
   S* nct;
   S* invt;
-  A* part;
-  S* pscal;
   unsigned* flags;
   int N, g, s, ln, co;  // item slot, component part, lane in the point, first component
 
@@ -130,18 +158,18 @@ struct WideRecursion {
     const auto o = Lay::offsets(N);
     Jt = reinterpret_cast<E*>(base + o.J);
     Mt = reinterpret_cast<E*>(base + o.mom);
+    Ml = Mt + (N + 1) * kS;  // complex: low parts of the prefix sums
     En = reinterpret_cast<E*>(base + o.epsn);
     nDht = reinterpret_cast<S*>(base + o.nDh);
     nct = reinterpret_cast<S*>(base + o.nc);
     invt = reinterpret_cast<S*>(base + o.inv);
-    part = reinterpret_cast<A*>(base + o.part);
-    pscal = reinterpret_cast<S*>(base + o.pscal);
     flags = reinterpret_cast<unsigned*>(base + o.flags);
   }
 
   __device__ __forceinline__ int rid(int i, int j) const { return range_idx(N, i, j); }
   __device__ __forceinline__ E& Jat(int r, int c) const { return Jt[r * kS + c]; }
   __device__ __forceinline__ E& Mat(int l, int c) const { return Mt[l * kS + c]; }
+  __device__ __forceinline__ E& Mlo(int l, int c) const { return Ml[l * kS + c]; }
   // one table row into registers with 16-byte LDS reads where the layout
   // allows (complex elements are 16 bytes; F_p rows of a padded layout start
   // on 16-byte boundaries)
@@ -171,24 +199,25 @@ struct WideRecursion {
   // this lane's components of a row
   __device__ __forceinline__ void loadJ(int r, E (&x)[DL]) const { load_row(Jt + r * kS + co, x); }
   __device__ __forceinline__ void loadM(int l, E (&x)[DL]) const { load_row(Mt + l * kS + co, x); }
-  // primed P_S (F_p: reduced, from prefix sums; complex: left-to-right sum of k')
+  // complex: prefix sum Q_l as its high and low parts
+  __device__ __forceinline__ void loadQ(int l, E (&h)[DL], E (&lo)[DL]) const {
+    load_row(Mt + l * kS + co, h);
+    load_row(Ml + l * kS + co, lo);
+  }
+  // complex: primed P of the legs between two prefix sums, (hb - ha) + (lb - la)
+  __device__ __forceinline__ static void dd_diff(const E (&ha)[DL], const E (&la)[DL], const E (&hb)[DL],
+                                                 const E (&lb)[DL], E (&P)[DL]) {
+#pragma unroll
+    for (int c = 0; c < DL; ++c) P[c] = cadd(csub(hb[c], ha[c]), csub(lb[c], la[c]));
+  }
+  // F_p: primed P_S, reduced, from prefix sums
   __device__ __forceinline__ void primedP(const Fld& F, int i, int j, E (&P)[DL]) const {
-    if constexpr (kFp) {
-      E a[DL], b[DL];
-      loadM(j + 1, a);
-      loadM(i, b);
+    E a[DL], b[DL];
+    loadM(j + 1, a);
+    loadM(i, b);
 #pragma unroll
-      for (int c = 0; c < DL; ++c) P[c] = F.esub(a[c], b[c]);
-      P[0] = F.prime0(P[0]);
-    } else {
-      loadM(i, P);
-      for (int l = i + 1; l <= j; ++l) {
-        E t[DL];
-        loadM(l, t);
-#pragma unroll
-        for (int c = 0; c < DL; ++c) P[c] = F.eadd(P[c], t[c]);
-      }
-    }
+    for (int c = 0; c < DL; ++c) P[c] = F.esub(a[c], b[c]);
+    P[0] = F.prime0(P[0]);
   }
   // F_p: primed P_S as unreduced differences Q_{j+1} - Q_i (|slot| <= 2h)
   __device__ __forceinline__ void lazyP(const Fld& F, int i, int j, E (&P)[DL]) const {
@@ -199,45 +228,8 @@ struct WideRecursion {
     for (int c = 0; c < DL; ++c) P[c] = a[c] - b[c];
     P[0] = F.prime0(P[0]);
   }
-  // complex: the primed momenta of both cuts c1 <= c2 of S = [i..j] in one
-  // pass over the legs, each leg read once and added to the sums it belongs
-  // to, every sum still taken left to right:
-  //   legs i..c1 -> A1 (and A2, which starts as A1);  c1+1..c2 -> B1, A2;
-  //   c2+1..j -> B1, B2
-  __device__ __forceinline__ void pair_momenta(int i, int j, int c1, int c2, E (&A1)[DL], E (&B1)[DL],
-                                               E (&A2)[DL], E (&B2)[DL]) const {
-#pragma unroll
-    for (int c = 0; c < DL; ++c) A1[c] = B1[c] = B2[c] = cplx{0.0, 0.0};
-    int l = i;
-    for (; l <= c1; ++l) {
-      E t[DL];
-      loadM(l, t);
-#pragma unroll
-      for (int c = 0; c < DL; ++c) A1[c] = cadd(A1[c], t[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < DL; ++c) A2[c] = A1[c];
-    for (; l <= c2; ++l) {
-      E t[DL];
-      loadM(l, t);
-#pragma unroll
-      for (int c = 0; c < DL; ++c) {
-        B1[c] = cadd(B1[c], t[c]);
-        A2[c] = cadd(A2[c], t[c]);
-      }
-    }
-    for (; l <= j; ++l) {
-      E t[DL];
-      loadM(l, t);
-#pragma unroll
-      for (int c = 0; c < DL; ++c) {
-        B1[c] = cadd(B1[c], t[c]);
-        B2[c] = cadd(B2[c], t[c]);
-      }
-    }
-  }
 
-  // ---- loads: eps into the table, momenta, eps_n; F_p prefix sums --------
+  // ---- loads: eps into the table, momenta, eps_n; prefix sums -------------
   __device__ void load(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad) {
     const int rows = (2 * N + 1) * DMAX;  // eps_0..eps_N, k_0..k_{N-1}
     for (int r = ln; r < rows; r += G * LC) {
@@ -249,26 +241,43 @@ struct WideRecursion {
       } else {
         const int l = which - N - 1;
         E k = Loader<Fld>::template get<MetricRT>(a, a.momenta, l, c, q, bad);
-        if constexpr (kFp) {
-          Mat(l + 1, c) = k;  // raw k_l, summed below
-        } else {
+        if constexpr (!kFp) {
           if (c == 0) k = F.prime0(k);
-          Mat(l, c) = k;
         }
+        Mat(l + 1, c) = k;  // raw (complex: primed) k_l, summed below
       }
     }
     if (ln == 0) *flags = 0u;
     group_sync();
-    if constexpr (kFp) {
-      if (g < DMAX) {  // prefix sums, one component per lane
+    if (ln < DMAX) {  // prefix sums, one component per lane
+      if constexpr (kFp) {
         E acc{};
-        Mat(0, g) = acc;
+        Mat(0, ln) = acc;
         for (int l = 0; l < N; ++l) {
-          acc = F.eadd(acc, Mat(l + 1, g));
-          Mat(l + 1, g) = acc;
+          acc = F.eadd(acc, Mat(l + 1, ln));
+          Mat(l + 1, ln) = acc;
+        }
+      } else {
+        // hi + lo = Q_l exactly up to the rounding of lo: hi takes the
+        // two-sum with each leg, lo collects the rounding errors
+        double hr = 0.0, hm = 0.0, lr = 0.0, lm = 0.0;
+        Mat(0, ln) = cplx{0.0, 0.0};
+        Mlo(0, ln) = cplx{0.0, 0.0};
+        for (int l = 0; l < N; ++l) {
+          const cplx k = Mat(l + 1, ln);
+          const double sr = hr + k.re, br = sr - hr;
+          lr += (hr - (sr - br)) + (k.re - br);
+          hr = sr;
+          const double sm = hm + k.im, bm = sm - hm;
+          lm += (hm - (sm - bm)) + (k.im - bm);
+          hm = sm;
+          Mat(l + 1, ln) = cplx{hr, hm};
+          Mlo(l + 1, ln) = cplx{lr, lm};
         }
       }
-      group_sync();
+    }
+    group_sync();
+    if constexpr (kFp) {
       for (int l = g; l < N; l += G) {  // nc(l) = P_l . eps_l
         E Pp[DL], e[DL];
         lazyP(F, l, l, Pp);
@@ -317,16 +326,13 @@ struct WideRecursion {
     }
   }
 
-  // ---- one work item: contributions of cut c to K'(S), S = [i..j] ---------
-  // cut3: the three-gluon split [i..c] | [c+1..j] and the adjacent-pair terms
-  // of the four-gluon vertex that involve this cut; cut4 below adds the
-  // four-gluon splits of one or two cuts.
-  // F_p: Pp holds P_S as unreduced differences, nDs accumulates -(J_A.J_B) / 2
-  // as an int64 sum of products; complex: PA, PB are the primed P_A, P_B
-  // (Pp unused), nDs sums -(J_A.J_B).
-  template <class NDS>
+  // ---- one three-gluon cut: contributions of cut c to K'(S), S = [i..j] ---
+  // the split [i..c] | [c+1..j] and the adjacent-pair terms of the four-gluon
+  // vertex that involve this cut.  F_p: Pp holds P_S as unreduced
+  // differences, nDs accumulates -(J_A.J_B) / 2 as an int64 sum of products;
+  // complex: PA, PB are the primed P_A, P_B (Pp unused), nDs sums -(J_A.J_B).
   __device__ void cut3(const Fld& F, int i, int j, int c, const E (&Pp)[DL], const E (&PA)[DL],
-                      const E (&PB)[DL], A (&K)[DL], NDS& nDs) const {
+                       const E (&PB)[DL], A (&K)[DL], NDS& nDs) const {
     E JA[DL], JB[DL];
     const int ra = rid(i, c), rb = rid(c + 1, j);
     loadJ(ra, JA);
@@ -341,7 +347,7 @@ struct WideRecursion {
       F.axpy(K, F.sneg(nc2), JB);
       F.axpy(K, nc3, JA);
       F.fold(K);
-      nDs = mad64(nDm, F.k.inv2, nDs);  // at most two terms per item
+      nDs = fp_fold(mad64(nDm, F.k.inv2, nDs), F.k);
     } else {
       E v[DL];
       const S n2 = F.ndot(PB, JA);
@@ -360,14 +366,13 @@ struct WideRecursion {
     F.fold(K);
   }
 
-  // four-gluon splits [i..c] | [c+1..t] | [t+1..j] of cut c1 (j - c1 - 1 of
-  // them), then of cut c2 (j - c2 - 1; none when c2 == c1), in one loop: the
-  // two cuts of a pair item have m - 2 splits together, so every lane of a
-  // round runs the same number of iterations (two loops back to back would
-  // run m - 2 + m/2 - 1, with lanes masked off).  Range indices advance
-  // incrementally: with e = (right end - left end) of a range, extending
-  // [c+1..t] to [c+1..t+1] adds N - e, and shrinking [t+1..j] to [t+2..j]
-  // adds e - N (from the index formula of range_idx).
+  // ---- four-gluon splits [i..c] | [c+1..t] | [t+1..j] of a pair of cuts --
+  // j - c1 - 1 splits of cut c1, then j - c2 - 1 of cut c2 (none when
+  // c2 == c1), in one loop: the two cuts of a pair have m - 2 splits together,
+  // so every lane of a round runs the same number of iterations.  Range
+  // indices advance incrementally: with e = (right end - left end) of a range,
+  // extending [c+1..t] to [c+1..t+1] adds N - e, and shrinking [t+1..j] to
+  // [t+2..j] adds e - N (from the index formula of range_idx).
   __device__ void cut4(const Fld& F, int i, int j, int c1, int c2, A (&K)[DL]) const {
     E JA[DL];
     loadJ(rid(i, c1), JA);
@@ -399,137 +404,129 @@ struct WideRecursion {
     F.fold(K);
   }
 
+  // the sums of the per items of each range (lanes LC apart), added in a
+  // butterfly: every lane of the range ends with the same total
+  template <int ST>
+  __device__ __forceinline__ void xor_step(const Fld& F, A (&K)[DL], NDS& nDs) const {
+#pragma unroll
+    for (int c = 0; c < DL; ++c) K[c] = add_acc(F, K[c], lane_xor<ST>(K[c]));
+    if constexpr (kFp) nDs = fp_fold(nDs + lane_xor<ST>(nDs), F.k);
+    else nDs = cadd(nDs, lane_xor<ST>(nDs));
+  }
+  __device__ __forceinline__ void range_sum(const Fld& F, A (&K)[DL], NDS& nDs, int per) const {
+    // per is the same in every lane of the wave (all its points have this N)
+    if constexpr (LC <= 32) if (per > 1) xor_step<LC>(F, K, nDs);
+    if constexpr (LC * 2 <= 32) if (per > 2) xor_step<LC * 2>(F, K, nDs);
+    if constexpr (LC * 4 <= 32) if (per > 4) xor_step<LC * 4>(F, K, nDs);
+    if constexpr (LC * 8 <= 32) if (per > 8) xor_step<LC * 8>(F, K, nDs);
+    if constexpr (LC * 16 <= 32) if (per > 16) xor_step<LC * 16>(F, K, nDs);
+    if constexpr (LC * 32 <= 32) if (per > 32) xor_step<LC * 32>(F, K, nDs);
+  }
+
   __device__ void run(const Fld& F, const LaunchArgs& a, int64_t q, S& result, E (&kroot)[DL]) {
     uint32_t bad = 0;
     bool singular = false;
     load(F, a, q, bad);
     inverses(F, singular);
     group_sync();
-    // complex: lane g owns [g..g+m-1] at every length m while g < N - m + 1,
-    // so it keeps that range's primed momentum as a running left-to-right sum
-    // (the same additions in the same order as summing the legs afresh)
-    [[maybe_unused]] E Pown[DL];
-    if constexpr (!kFp) {
-      if (g < N) loadM(g, Pown);
-    }
 
-    const bool pairs = kPairsAlways || (kPairsMaybe && a.wide_pairs != 0);
     for (int m = 2; m <= N; ++m) {
-      const int nr = N - m + 1;                 // ranges of length m: i = 0 .. nr-1
-      const int per = pairs ? m / 2 : m - 1;    // items per range
-      const int items = nr * per;
-      const bool own = g < nr;
-      const int oi = g, oj = g + m - 1;         // the range this lane owns
-      A K[DL];
+      const int nr = N - m + 1;        // ranges of length m: i = 0 .. nr-1
+      const int pairs = m / 2;         // items per range: cuts c and i + j - 1 - c
+      int lg = 0;                      // per = 2^lg item slots per range
+      while ((1 << lg) < pairs) ++lg;
+      const int per = 1 << lg, rpr = G >> lg;  // ranges per round
+      const int rl = g >> lg, u = g & (per - 1);
+      for (int r0 = 0; r0 < nr; r0 += rpr) {  // rounds of G / per ranges
+        const int r = r0 + rl;
+        const bool act = r < nr && u < pairs;
+        A K[DL];
 #pragma unroll
-      for (int c = 0; c < DL; ++c) K[c] = F.azero();
-      S nDsum = F.szero();
-      for (int k0 = 0; k0 < items; k0 += G) {
-        const int k = k0 + g;
-        if (k < items) {
-          const int i = k / per, u = k % per, j = i + m - 1;
+        for (int c = 0; c < DL; ++c) K[c] = F.azero();
+        NDS nDs{};
+        if (act) {
+          const int i = r, j = r + m - 1;
+          const int c1 = i + u, c2 = j - 1 - u;
           E Pp[DL];
-          if constexpr (kFp) lazyP(F, i, j, Pp);
-          A Kp[DL];
-#pragma unroll
-          for (int c = 0; c < DL; ++c) Kp[c] = F.azero();
-          const int c1 = i + u, c2 = pairs ? j - 1 - u : c1;
           if constexpr (kFp) {
-            int64_t nDs = 0;
-            cut3(F, i, j, c1, Pp, Pp, Pp, Kp, nDs);
-            if (pairs && c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, Kp, nDs);
-            cut4(F, i, j, c1, c2, Kp);
-            pscal[g] = fp_redc2(fp_fold(nDs, F.k), F.k);  // -(sum of J_A.J_B) / 2
+            lazyP(F, i, j, Pp);
+            cut3(F, i, j, c1, Pp, Pp, Pp, K, nDs);
+            if (c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, K, nDs);
           } else {
-            S nDs = F.szero();
-            if (pairs) {
-              E PA1[DL], PB1[DL], PA2[DL], PB2[DL];
-              pair_momenta(i, j, c1, c2, PA1, PB1, PA2, PB2);
-              cut3(F, i, j, c1, Pp, PA1, PB1, Kp, nDs);
-              if (c2 != c1) cut3(F, i, j, c2, Pp, PA2, PB2, Kp, nDs);
+            E Qih[DL], Qil[DL], Qjh[DL], Qjl[DL], Qch[DL], Qcl[DL], PA[DL], PB[DL];
+            loadQ(i, Qih, Qil);
+            loadQ(j + 1, Qjh, Qjl);
+            loadQ(c1 + 1, Qch, Qcl);
+            dd_diff(Qih, Qil, Qch, Qcl, PA);
+            dd_diff(Qch, Qcl, Qjh, Qjl, PB);
+            cut3(F, i, j, c1, Pp, PA, PB, K, nDs);
+            if (c2 != c1) {
+              loadQ(c2 + 1, Qch, Qcl);
+              dd_diff(Qih, Qil, Qch, Qcl, PA);
+              dd_diff(Qch, Qcl, Qjh, Qjl, PB);
+              cut3(F, i, j, c2, Pp, PA, PB, K, nDs);
+            }
+          }
+          cut4(F, i, j, c1, c2, K);
+        }
+        range_sum(F, K, nDs, per);
+        if (act && u == 0) {  // the range's first item finishes it
+          const int oi = r, oj = r + m - 1;
+          const bool root = (m == N);
+          S nDhS;
+          E Pp[DL];
+          if constexpr (kFp) {
+            nDhS = fp_redc2(fp_fold(nDs, F.k), F.k);  // the cuts' sums already carry the factor 1/2
+            lazyP(F, oi, oj, Pp);
+            // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
+            E QQ[DL];
+#pragma unroll
+            for (int c = 0; c < DL; ++c) QQ[c] = Mat(oi, co + c) + Mat(oj + 1, co + c);  // once per range
+            F.axpy(K, nDhS, QQ);
+            F.fold(K);
+          } else {
+            nDhS = Rec::half_scalar(F, nDs);
+            E Qih[DL], Qil[DL], Qjh[DL], Qjl[DL];
+            loadQ(oi, Qih, Qil);
+            loadQ(oj + 1, Qjh, Qjl);
+            dd_diff(Qih, Qil, Qjh, Qjl, Pp);
+          }
+          if (!root) {
+            const int id = rid(oi, oj);
+            nDht[id] = nDhS;
+            E Jn[DL];
+            if constexpr (kFp) {
+              const S inv2 = invt[id];
+#pragma unroll
+              for (int c = 0; c < DL; ++c) {
+                Jn[c] = F.finish_mul32(K[c], inv2);
+                Jat(id, co + c) = Jn[c];
+              }
+              nct[id] = F.template ndot<4>(Pp, Jn);
             } else {
-              E PA[DL], PB[DL];
-              primedP(F, i, c1, PA);
-              primedP(F, c1 + 1, j, PB);
-              cut3(F, i, j, c1, Pp, PA, PB, Kp, nDs);
+              E Pu[DL];
+#pragma unroll
+              for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
+              Pu[0] = F.prime0(Pp[0]);
+              const S y = F.ndot(Pp, Pu);
+              const S inv2 = Rec::c_inverse_times(y, -2.0, singular);
+#pragma unroll
+              for (int c = 0; c < DL; ++c) {
+                Jn[c] = F.mul(F.finish(K[c]), inv2);
+                Jat(id, co + c) = Jn[c];
+              }
             }
-            cut4(F, i, j, c1, c2, Kp);
-            if (s == 0) pscal[g] = nDs;
-          }
-#pragma unroll
-          for (int c = 0; c < DL; ++c) part[g * kS + co + c] = Kp[c];
-        }
-        group_sync();
-        if (own) {
-          // this round's items of the owned range, in item (= cut) order
-          const int lo = max(k0, oi * per), hi = min(k0 + G, (oi + 1) * per);
-          for (int kk = lo; kk < hi; ++kk) {
-            const int slot = kk - k0;
-#pragma unroll
-            for (int c = 0; c < DL; ++c) K[c] = add_acc(F, K[c], part[slot * kS + co + c]);
-            nDsum = Rec::accumulate_scalar(F, nDsum, pscal[slot]);
-          }
-        }
-        group_sync();
-      }
-      if (own) {
-        const bool root = (m == N);
-        S nDhS;
-        E Pp[DL];
-        if constexpr (kFp) {
-          nDhS = nDsum;  // the items' sums already carry the factor 1/2
-          lazyP(F, oi, oj, Pp);
-          // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
-          E QQ[DL];
-#pragma unroll
-          for (int c = 0; c < DL; ++c) QQ[c] = Mat(oi, co + c) + Mat(oj + 1, co + c);  // once per range
-          F.axpy(K, nDhS, QQ);
-          F.fold(K);
-        } else {
-          nDhS = Rec::half_scalar(F, nDsum);
-          E t[DL];
-          loadM(oj, t);
-#pragma unroll
-          for (int c = 0; c < DL; ++c) {
-            Pown[c] = F.eadd(Pown[c], t[c]);
-            Pp[c] = Pown[c];
-          }
-        }
-        if (!root) {
-          const int id = rid(oi, oj);
-          nDht[id] = nDhS;
-          E Jn[DL];
-          if constexpr (kFp) {
-            const S inv2 = invt[id];
-#pragma unroll
-            for (int c = 0; c < DL; ++c) {
-              Jn[c] = F.finish_mul32(K[c], inv2);
-              Jat(id, co + c) = Jn[c];
-            }
-            nct[id] = F.template ndot<4>(Pp, Jn);
           } else {
-            E Pu[DL];
-#pragma unroll
-            for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
-            Pu[0] = F.prime0(Pp[0]);
-            const S y = F.ndot(Pp, Pu);
-            const S inv2 = Rec::c_inverse_times(y, -2.0, singular);
+            E Kf[DL], en[DL];
 #pragma unroll
             for (int c = 0; c < DL; ++c) {
-              Jn[c] = F.mul(F.finish(K[c]), inv2);
-              Jat(id, co + c) = Jn[c];
+              Kf[c] = F.finish(K[c]);
+              en[c] = En[co + c];
             }
-          }
-        } else {
-          E Kf[DL], en[DL];
+            result = F.ndot_u(en, Kf);
 #pragma unroll
-          for (int c = 0; c < DL; ++c) {
-            Kf[c] = F.finish(K[c]);
-            en[c] = En[co + c];
+            for (int c = 0; c < DL; ++c) kroot[c] = Kf[c];
           }
-          result = F.ndot_u(en, Kf);
-#pragma unroll
-          for (int c = 0; c < DL; ++c) kroot[c] = Kf[c];
         }
       }
       group_sync();
