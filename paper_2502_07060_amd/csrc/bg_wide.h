@@ -53,6 +53,7 @@
 
 #include <type_traits>
 
+#include "bg.h"
 #include "bg_generic.h"
 
 namespace bg {
@@ -229,33 +230,63 @@ struct WideRecursion {
     P[0] = F.prime0(P[0]);
   }
 
+  // F_p: lazyP, and Q_i + Q_{j+1} unreduced (|slot| <= 2h) from the same rows
+  __device__ __forceinline__ void lazyPQ(const Fld& F, int i, int j, E (&P)[DL], E (&QQ)[DL]) const {
+    E a[DL], b[DL];
+    loadM(j + 1, a);
+    loadM(i, b);
+#pragma unroll
+    for (int c = 0; c < DL; ++c) {
+      P[c] = a[c] - b[c];
+      QQ[c] = a[c] + b[c];
+    }
+    P[0] = F.prime0(P[0]);
+  }
+
   // ---- loads: eps into the table, momenta, eps_n; prefix sums -------------
   __device__ void load(const Fld& F, const LaunchArgs& a, int64_t q, uint32_t& bad) {
-    const int rows = (2 * N + 1) * DMAX;  // eps_0..eps_N, k_0..k_{N-1}
-    for (int r = ln; r < rows; r += G * LC) {
-      const int which = r / DMAX, c = r % DMAX;
-      if (which <= N) {
-        const E e = Loader<Fld>::template get<MetricRT>(a, a.pols, which, c, q, bad);
-        if (which < N) Jat(rid(which, which), c) = e;
-        else En[c] = e;
-      } else {
-        const int l = which - N - 1;
-        E k = Loader<Fld>::template get<MetricRT>(a, a.momenta, l, c, q, bad);
-        if constexpr (!kFp) {
-          if (c == 0) k = F.prime0(k);
-        }
-        Mat(l + 1, c) = k;  // raw (complex: primed) k_l, summed below
+    // every global load of the point first (a fixed count per lane, the
+    // ones past the last row repeat row 0), then the LDS stores
+    constexpr int kLegs = BG_MAX_N - 1;                        // N <= 13
+    constexpr int kRowsMax = (2 * kLegs + 1) * DMAX;           // eps_0..eps_N, k_0..k_{N-1}
+    constexpr int kIt = (kRowsMax + G * LC - 1) / (G * LC);
+    const int rows = (2 * N + 1) * DMAX;
+    E v[kIt];
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+      const int r = ln + t * G * LC;
+      const int rr = r < rows ? r : 0;
+      const int which = rr / DMAX, c = rr % DMAX;
+      const bool eps = which <= N;
+      v[t] = Loader<Fld>::template get<MetricRT>(a, eps ? a.pols : a.momenta, eps ? which : which - N - 1, c, q,
+                                                 bad);
+    }
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+      const int r = ln + t * G * LC;
+      if (r < rows) {
+        const int which = r / DMAX, c = r % DMAX;
+        // eps_l into the table, eps_n aside, raw k_l (complex: primed,
+        // which is the identity) into the prefix-sum rows, summed below
+        E* dst = which < N ? &Jat(rid(which, which), c) : (which == N ? &En[c] : &Mat(which - N, c));
+        *dst = v[t];
       }
     }
     if (ln == 0) *flags = 0u;
     group_sync();
-    if (ln < DMAX) {  // prefix sums, one component per lane
+    if (ln < DMAX) {  // prefix sums, one component per lane: all legs read first
+      E k[kLegs];
+#pragma unroll
+      for (int l = 0; l < kLegs; ++l) k[l] = l < N ? Mat(l + 1, ln) : E{};
       if constexpr (kFp) {
         E acc{};
         Mat(0, ln) = acc;
-        for (int l = 0; l < N; ++l) {
-          acc = F.eadd(acc, Mat(l + 1, ln));
-          Mat(l + 1, ln) = acc;
+#pragma unroll
+        for (int l = 0; l < kLegs; ++l) {
+          if (l < N) {
+            acc = F.eadd(acc, k[l]);
+            Mat(l + 1, ln) = acc;
+          }
         }
       } else {
         // hi + lo = Q_l exactly up to the rounding of lo: hi takes the
@@ -263,16 +294,18 @@ struct WideRecursion {
         double hr = 0.0, hm = 0.0, lr = 0.0, lm = 0.0;
         Mat(0, ln) = cplx{0.0, 0.0};
         Mlo(0, ln) = cplx{0.0, 0.0};
-        for (int l = 0; l < N; ++l) {
-          const cplx k = Mat(l + 1, ln);
-          const double sr = hr + k.re, br = sr - hr;
-          lr += (hr - (sr - br)) + (k.re - br);
-          hr = sr;
-          const double sm = hm + k.im, bm = sm - hm;
-          lm += (hm - (sm - bm)) + (k.im - bm);
-          hm = sm;
-          Mat(l + 1, ln) = cplx{hr, hm};
-          Mlo(l + 1, ln) = cplx{lr, lm};
+#pragma unroll
+        for (int l = 0; l < kLegs; ++l) {
+          if (l < N) {
+            const double sr = hr + k[l].re, br = sr - hr;
+            lr += (hr - (sr - br)) + (k[l].re - br);
+            hr = sr;
+            const double sm = hm + k[l].im, bm = sm - hm;
+            lm += (hm - (sm - bm)) + (k[l].im - bm);
+            hm = sm;
+            Mat(l + 1, ln) = cplx{hr, hm};
+            Mlo(l + 1, ln) = cplx{lr, lm};
+          }
         }
       }
     }
@@ -444,18 +477,31 @@ struct WideRecursion {
 #pragma unroll
         for (int c = 0; c < DL; ++c) K[c] = F.azero();
         NDS nDs{};
+        // what the range's finish needs and K does not (P_S, the propagator
+        // inverse, F_p: Q_i + Q_{j+1}): formed before the cuts, so that its
+        // loads and the division overlap their work
+        E Pp[DL], QQ[DL];
+        S inv2{};
         if (act) {
           const int i = r, j = r + m - 1;
           const int c1 = i + u, c2 = j - 1 - u;
-          E Pp[DL];
           if constexpr (kFp) {
-            lazyP(F, i, j, Pp);
+            lazyPQ(F, i, j, Pp, QQ);
+            if (m < N) inv2 = invt[rid(i, j)];
             cut3(F, i, j, c1, Pp, Pp, Pp, K, nDs);
             if (c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, K, nDs);
           } else {
             E Qih[DL], Qil[DL], Qjh[DL], Qjl[DL], Qch[DL], Qcl[DL], PA[DL], PB[DL];
             loadQ(i, Qih, Qil);
             loadQ(j + 1, Qjh, Qjl);
+            dd_diff(Qih, Qil, Qjh, Qjl, Pp);
+            if (m < N) {  // the root has no propagator
+              E Pu[DL];
+#pragma unroll
+              for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
+              Pu[0] = F.prime0(Pp[0]);
+              inv2 = Rec::c_inverse_times(F.ndot(Pp, Pu), -2.0, singular);
+            }
             loadQ(c1 + 1, Qch, Qcl);
             dd_diff(Qih, Qil, Qch, Qcl, PA);
             dd_diff(Qch, Qcl, Qjh, Qjl, PB);
@@ -471,51 +517,26 @@ struct WideRecursion {
         }
         range_sum(F, K, nDs, per);
         if (act && u == 0) {  // the range's first item finishes it
-          const int oi = r, oj = r + m - 1;
-          const bool root = (m == N);
+          const int id = rid(r, r + m - 1);
           S nDhS;
-          E Pp[DL];
           if constexpr (kFp) {
             nDhS = fp_redc2(fp_fold(nDs, F.k), F.k);  // the cuts' sums already carry the factor 1/2
-            lazyP(F, oi, oj, Pp);
-            // -Dh(S) (Q_i + Q_{j+1}), the prefix sums added unreduced (|.| <= 2h)
-            E QQ[DL];
-#pragma unroll
-            for (int c = 0; c < DL; ++c) QQ[c] = Mat(oi, co + c) + Mat(oj + 1, co + c);  // once per range
+            // -Dh(S) (Q_i + Q_{j+1})
             F.axpy(K, nDhS, QQ);
             F.fold(K);
           } else {
             nDhS = Rec::half_scalar(F, nDs);
-            E Qih[DL], Qil[DL], Qjh[DL], Qjl[DL];
-            loadQ(oi, Qih, Qil);
-            loadQ(oj + 1, Qjh, Qjl);
-            dd_diff(Qih, Qil, Qjh, Qjl, Pp);
           }
-          if (!root) {
-            const int id = rid(oi, oj);
+          if (m < N) {
             nDht[id] = nDhS;
             E Jn[DL];
-            if constexpr (kFp) {
-              const S inv2 = invt[id];
 #pragma unroll
-              for (int c = 0; c < DL; ++c) {
-                Jn[c] = F.finish_mul32(K[c], inv2);
-                Jat(id, co + c) = Jn[c];
-              }
-              nct[id] = F.template ndot<4>(Pp, Jn);
-            } else {
-              E Pu[DL];
-#pragma unroll
-              for (int c = 0; c < DL; ++c) Pu[c] = Pp[c];
-              Pu[0] = F.prime0(Pp[0]);
-              const S y = F.ndot(Pp, Pu);
-              const S inv2 = Rec::c_inverse_times(y, -2.0, singular);
-#pragma unroll
-              for (int c = 0; c < DL; ++c) {
-                Jn[c] = F.mul(F.finish(K[c]), inv2);
-                Jat(id, co + c) = Jn[c];
-              }
+            for (int c = 0; c < DL; ++c) {
+              if constexpr (kFp) Jn[c] = F.finish_mul32(K[c], inv2);
+              else Jn[c] = F.mul(F.finish(K[c]), inv2);
+              Jat(id, co + c) = Jn[c];
             }
+            if constexpr (kFp) nct[id] = F.template ndot<4>(Pp, Jn);
           } else {
             E Kf[DL], en[DL];
 #pragma unroll
