@@ -253,13 +253,21 @@ int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momen
 }
 
 int wide_points_per_block(const Variant& v, size_t per) {
-  // G lanes per point: the block size whose blocks hold the most points per CU
+  // G lanes per point: the block size whose blocks hold the most points per
+  // CU (LDS and 32 wave slots per CU), among blocks of whole wavefronts when
+  // one fits: a block of fewer lanes than a wave still takes a wave slot and
+  // issues every instruction for 64 lanes, so half-full waves halve the work
+  // done per instruction
   const int maxlds = max_lds_per_block();
   const int pmax = std::min<int>(256 / v.L, (int)((size_t)maxlds / per));
+  const int step = v.L < 64 ? 64 / v.L : 1;  // points per whole wave
+  const int first = step <= pmax ? step : 1;
+  const int inc = step <= pmax ? step : 1;
   int P = 1;
   long bestres = 0;
-  for (int c = 1; c <= pmax; ++c) {
-    const long blocks = std::min<long>((long)maxlds / ((long)c * (long)per), 2048 / ((long)c * v.L));
+  for (int c = first; c <= pmax; c += inc) {
+    const long waves = ((long)c * v.L + 63) / 64;
+    const long blocks = std::min<long>((long)maxlds / ((long)c * (long)per), 32 / waves);
     const long res = blocks * c;
     if (res > bestres || (res == bestres && c > P)) { bestres = res; P = c; }
   }

@@ -100,8 +100,9 @@ constexpr unsigned kQueueLdsHeader = 16;  // LDS bytes before the points' tables
 // the compiler then waits for each load of the alternating body before
 // issuing the next, which makes that metric about twice as slow.  The complex
 // register kernel and the runtime-n kernels take MetricRT: one body, where
-// the map is a select (complex) or a product with a.ialt, which is R in the
-// mostly-minus metric (F_p).
+// the map is a select (complex) or, over F_p, one Montgomery product per
+// loaded component, with a.ialt for components 2, 4, ... (R in the
+// mostly-minus metric) and with R for the others.
 enum : int { MetricMM = 0, MetricAlt = 1, MetricRT = 2 };
 
 template <class Fld>
@@ -120,8 +121,11 @@ struct Loader<FpField<DL, L, SC>> {
     const uint32_t xc = xi < (uint32_t)a.fp.p ? xi : 0u;
     const bool rot = mu >= 2 && (mu & 1) == 0;
     if constexpr (M == MetricRT) {
-      // both balanced: the product with R is the conversion, bit for bit
-      return rot ? fp_mul((int32_t)xc, a.ialt, a.fp) : fp_from_canonical(xc, a.fp);
+      // one product for every component, with R (the conversion, bit for bit:
+      // both results are balanced) or with a.ialt: a select between a product
+      // and the conversion became a branch around each load, which then
+      // waited for every load before issuing the next
+      return fp_mul((int32_t)xc, rot ? a.ialt : a.fp.one, a.fp);
     } else {
       int32_t v = fp_from_canonical(xc, a.fp);
       if constexpr (M == MetricAlt) {  // a select, so that the loads stay in one block
