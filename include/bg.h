@@ -150,6 +150,9 @@ enum { BG_METRIC_MOSTLY_MINUS = 0, BG_METRIC_ALTERNATING = 1 };
  * is loaded, which turns every product into the mostly-minus one; over Z_p
  * this needs p = 1 (mod 4) (BG_EDOMAIN otherwise), with i = g^((p-1)/4) for
  * the smallest quadratic non-residue g (M does not depend on the choice).
+ * Over Z_p, alternating-metric calls whose selected kernel is a one-lane
+ * register kernel run the two-lane one of the same (n, d): its alternating
+ * form is the faster of the two.
  */
 int bg_amplitudes_c128_metric(int metric, int n, int d, int64_t npts, int64_t ld,
                               const double* momenta, const double* pols,

@@ -57,8 +57,9 @@ FpConst make_fp_const(uint32_t p);
 // a square root of -1 mod p (p = 1 mod 4) times R = 2^64, balanced
 int32_t fp_sqrt_minus_one_mont(uint32_t p);
 bool is_prime_u32(uint32_t n);
+// force: the variant to launch instead of the one selected for (field, n, d)
 int prepare(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
-            void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec);
+            void* out, uint8_t* status, const FpConst& fp, LaunchSpec& spec, const Variant* force = nullptr);
 int enqueue(LaunchSpec& spec, hipStream_t stream);
 // lane-group launches: points per block for LDS bytes per point `per`, the
 // one that keeps the most points resident per CU
