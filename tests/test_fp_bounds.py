@@ -581,7 +581,7 @@ def test_register_kernel_replay_catches_a_missing_fold():
 # lane-group kernel (csrc/bg_wide.h, Z_p path) and one-point-per-lane kernel
 # (csrc/bg_generic.h): L = 1 or 2 lanes per item, balanced scalars
 # ---------------------------------------------------------------------------
-def replay_lane_group_kernel(p, N, DL, LC, pairs):
+def replay_lane_group_kernel(p, N, DL, LC):
     B = Bounds(p)
     F = FieldModel(B, DL, LC)
     h = B.h
@@ -590,43 +590,50 @@ def replay_lane_group_kernel(p, N, DL, LC, pairs):
     nc = max(nc, F.ndot(lazyP, h, UX=4))          # ranges: ndot<4>, balanced
     F.ndot(h, h)                                  # propagators
     for m in range(2, N + 1):
-        per = m // 2 if pairs else m - 1
-        owner = 0                                 # owner's accumulator
-        first = True
-        for u in range(per):
-            Kp = Vec(B)
-            nDs = 0
-            for _cut in range(2 if pairs else 1):
-                nDm = F.ndot(h, h)
-                nc2 = F.ndot_sub(lazyP, h, nc, UX=4)
-                nc3 = F.ndot_sub(lazyP, h, nc, UX=4)
-                Kp.axpy(nDm, h)
-                Kp.axpy(nc2, h)
-                Kp.axpy(nc3, h)
-                Kp.fold()
-                nDs = B.chk(nDs + nDm * h, "nDs")
-                Kp.axpy(h, h)                     # adjacent-pair terms
-                Kp.axpy(h, h)
-                Kp.fold()
-            cnt = 0
-            for _q in range(max(0, m - 2)):       # four-gluon splits of the item
-                ne = F.ndot(h, h)
-                Kp.axpy(ne, h)
-                cnt += 1
-                if cnt == 5:
-                    Kp.fold()
-                    cnt = 0
+        pairs = m // 2                            # items per range: a pair of cuts each
+        per = 1
+        while per < pairs:                        # item slots per range (a power of two)
+            per *= 2
+        # every item: two three-gluon cuts (the middle item of an odd number
+        # of cuts has one; two is the larger bound), then m - 2 splits
+        Kp = Vec(B)
+        nDs = 0
+        for _cut in range(2):
+            nDm = F.ndot(h, h)
+            nc2 = F.ndot_sub(lazyP, h, nc, UX=4)
+            nc3 = F.ndot_sub(lazyP, h, nc, UX=4)
+            Kp.axpy(nDm, h)
+            Kp.axpy(nc2, h)
+            Kp.axpy(nc3, h)
             Kp.fold()
-            B.redc2(B.fold(nDs))
-            # the owner adds the item's partial and refolds (add_acc)
-            owner = Kp.b if first else B.fold(B.chk(owner + Kp.b, "add_acc"))
-            first = False
+            nDs = B.fold(B.chk(nDs + nDm * h, "nDs"))  # folded after every cut
+            Kp.axpy(h, h)                         # adjacent-pair terms
+            Kp.axpy(h, h)
+            Kp.fold()
+        cnt = 0
+        for _q in range(max(0, m - 2)):           # four-gluon splits of the item
+            ne = F.ndot(h, h)
+            Kp.axpy(ne, h)
+            cnt += 1
+            if cnt == 5:
+                Kp.fold()
+                cnt = 0
+        Kp.fold()
+        # the range's slots add their sums in a butterfly, refolding after
+        # every step (add_acc); every slot may hold a worst-case sum
+        acc, nd = Kp.b, nDs
+        s = 1
+        while s < per:
+            acc = B.fold(B.chk(acc + acc, "butterfly"))
+            nd = B.fold(B.chk(nd + nd, "butterfly nDs"))
+            s *= 2
+        B.redc2(B.fold(nd))
         K = Vec(B)
-        K.b = owner
+        K.b = acc
         K.axpy(h, 2 * h)                          # -Dh(S)(Q_i + Q_{j+1})
         K.fold()
-        s = B.redc1(B.fold(K.b))
-        B.redc2(B.chk(s * h, "finish_mul32"))
+        s1 = B.redc1(B.fold(K.b))
+        B.redc2(B.chk(s1 * h, "finish_mul32"))
         B.redc2(B.fold(K.b))
 
 
@@ -672,8 +679,7 @@ def test_runtime_n_kernel_schedules(p):
         if f != "fp":
             continue
         for N in range(2, 14):
-            replay_lane_group_kernel(p, N, dm // LC, LC, pairs=(G == 16))
-            replay_lane_group_kernel(p, N, dm // LC, LC, pairs=False)
+            replay_lane_group_kernel(p, N, dm // LC, LC)
     for f, dm in b.GENERIC_VARIANTS:
         if f == "fp":
             for N in range(2, 14):
