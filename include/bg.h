@@ -470,8 +470,17 @@ typedef struct {
 int bg_variants(int field, int n, int d, bg_variant_info* out, int cap);
 
 /* Pins variant `index` (from bg_variants) for (field, n, d); index -1 restores
- * the default choice.  BG_EINVAL if the index does not fit (field, n, d). */
+ * the default choice.  BG_EINVAL if the index does not fit (field, n, d).
+ * This is the selection of the mostly-minus metric, the one bg_variants
+ * reports as `selected`. */
 int bg_select_variant(int field, int n, int d, int index);
+
+/* The same for launches in metric BG_METRIC_* (paper Sec. 3.1): the two
+ * metric forms of one kernel can run at different speeds, so alternating-
+ * metric launches have pins of their own.  Without one they take the
+ * mostly-minus selection (over Z_p with a one-lane register kernel replaced
+ * by the two-lane one).  BG_EINVAL for an unknown metric. */
+int bg_select_variant_metric(int metric, int field, int n, int d, int index);
 
 /*
  * bg_autotune -- times every variant compiled for (field, n, d) on npts
@@ -487,12 +496,20 @@ int bg_select_variant(int field, int n, int d, int index);
 int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps,
                 double* ms_out, int cap, void* hip_stream);
 
-/* Writes the pinned selections to a text file (one line per (field, n, d),
- * naming the kernel by lanes, components per lane, LDS tables, generic). */
+/* bg_autotune in metric BG_METRIC_* (BG_EINVAL otherwise): times the launches
+ * in that metric and pins the fastest for it (bg_select_variant_metric).
+ * Over Z_p the alternating metric needs p = 1 (mod 4) (BG_EDOMAIN). */
+int bg_autotune_metric(int metric, int field, int n, int d, uint32_t p, int64_t npts, int reps,
+                       double* ms_out, int cap, void* hip_stream);
+
+/* Writes the pinned selections of both metrics to a text file (one line per
+ * pinned (field, n, d, metric), naming the kernel by lanes, components per
+ * lane, LDS tables, generic, padded, max_d; the metric is the last column). */
 int bg_tune_save(const char* path);
 
-/* Applies selections written by bg_tune_save; returns how many matched a
- * compiled kernel, or a negative error code. */
+/* Applies selections written by bg_tune_save (a line without the metric
+ * column pins the mostly-minus metric); returns how many matched a compiled
+ * kernel, or a negative error code. */
 int bg_tune_load(const char* path);
 
 /*

@@ -76,8 +76,13 @@ _SIGNATURES = {
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bg_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "bg_select_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "bg_select_variant_metric": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int]),
     "bg_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_int64,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "bg_autotune_metric": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                                          ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_void_p]),
     "bg_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "bg_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bg_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
@@ -152,21 +157,33 @@ def bg_variants(field: int, n: int, d: int):
     return [{k: getattr(arr[i], k) for k, _ in bg_variant_info._fields_} for i in range(cnt)]
 
 
-def bg_select_variant(field: int, n: int, d: int, index: int) -> None:
-    rc = lib().bg_select_variant(field, n, d, index)
+def bg_select_variant(field: int, n: int, d: int, index: int, metric=None) -> None:
+    """Pin variant `index` for (field, n, d): for the mostly-minus metric, or
+    for `metric` (BG_METRIC_*) when given."""
+    if metric is None:
+        rc = lib().bg_select_variant(field, n, d, index)
+    else:
+        rc = lib().bg_select_variant_metric(int(metric), field, n, d, index)
     if rc != BG_OK:
-        raise BGError(rc, "bg_select_variant")
+        raise BGError(rc, "bg_select_variant" if metric is None else "bg_select_variant_metric")
 
 
-def bg_autotune(field: int, n: int, d: int, p: int = 0, npts: int = 1 << 18, reps: int = 5, stream=None):
+def bg_autotune(field: int, n: int, d: int, p: int = 0, npts: int = 1 << 18, reps: int = 5, stream=None,
+                metric=None):
     """Time every variant for (field, n, d), pin the fastest; returns
-    (chosen index, [(variant dict, ms per launch), ...])."""
+    (chosen index, [(variant dict, ms per launch), ...]).  With `metric`
+    (BG_METRIC_*) the launches run in that metric and the pin is that
+    metric's (bg_autotune_metric)."""
     vs = bg_variants(field, n, d)
     ms = (ctypes.c_double * max(len(vs), 1))()
-    rc = lib().bg_autotune(field, n, d, ctypes.c_uint32(p), npts, reps, ctypes.cast(ms, ctypes.c_void_p),
-                           len(vs), _stream_ptr(stream))
+    if metric is None:
+        rc = lib().bg_autotune(field, n, d, ctypes.c_uint32(p), npts, reps, ctypes.cast(ms, ctypes.c_void_p),
+                               len(vs), _stream_ptr(stream))
+    else:
+        rc = lib().bg_autotune_metric(int(metric), field, n, d, ctypes.c_uint32(p), npts, reps,
+                                      ctypes.cast(ms, ctypes.c_void_p), len(vs), _stream_ptr(stream))
     if rc < 0:
-        raise BGError(rc, "bg_autotune")
+        raise BGError(rc, "bg_autotune" if metric is None else "bg_autotune_metric")
     return rc, [(v, ms[i]) for i, v in enumerate(vs)]
 
 

@@ -11,8 +11,6 @@
 
 namespace bg {
 
-bool is_pinned(int field, int n, int d);
-
 std::vector<Variant>& registry() {
   static std::vector<Variant> r;
   return r;
@@ -115,20 +113,41 @@ static bool fits(const Variant& v, int field, int n, int d) {
   return v.N == n - 1 && v.DL * v.L >= d;
 }
 
+// selections, per metric: launches in the alternating metric have pins of
+// their own (a kernel's two metric forms can compile to code of different
+// speed), and fall back to the mostly-minus choice
 struct Pin {
-  int field, n, d, index;
+  int field, n, d, metric, index;
 };
 static std::mutex g_pin_mu;
 static std::vector<Pin> g_pins;
 
-static int pinned(int field, int n, int d) {
+static int pinned(int field, int n, int d, int metric) {
   std::lock_guard<std::mutex> lk(g_pin_mu);
   for (const Pin& p : g_pins)
-    if (p.field == field && p.n == n && p.d == d) return p.index;
+    if (p.field == field && p.n == n && p.d == d && p.metric == metric) return p.index;
   return -1;
 }
 
-bool is_pinned(int field, int n, int d) { return pinned(field, n, d) >= 0; }
+bool is_pinned(int field, int n, int d, int metric) { return pinned(field, n, d, metric) >= 0; }
+
+int pinned_index(int field, int n, int d, int metric) { return pinned(field, n, d, metric); }
+
+int select_variant(int metric, int field, int n, int d, int index) {
+  if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
+  if (metric != BG_METRIC_MOSTLY_MINUS && metric != BG_METRIC_ALTERNATING) return BG_EINVAL;
+  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
+  if (index >= 0 && (index >= (int)registry().size() || !fits(registry()[index], field, n, d)))
+    return BG_EINVAL;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  for (auto it = g_pins.begin(); it != g_pins.end(); ++it)
+    if (it->field == field && it->n == n && it->d == d && it->metric == metric) {
+      g_pins.erase(it);
+      break;
+    }
+  if (index >= 0) g_pins.push_back({field, n, d, metric, index});
+  return BG_OK;
+}
 
 const Variant* default_variant(int field, int n, int d);
 
@@ -139,7 +158,7 @@ static bool best_fills(const Variant* v, int N) {
 }
 
 const Variant* choose_variant(int field, int n, int d) {
-  const int idx = pinned(field, n, d);
+  const int idx = pinned(field, n, d, BG_METRIC_MOSTLY_MINUS);
   if (idx >= 0 && idx < (int)registry().size() && fits(registry()[idx], field, n, d))
     return &registry()[idx];
   return default_variant(field, n, d);
@@ -282,12 +301,13 @@ int enqueue(LaunchSpec& spec, hipStream_t stream) {
   return e == hipSuccess ? BG_OK : BG_EHIP;
 }
 
-// The alternating-metric body of a one-lane F_p register kernel runs about
-// twice as long as its mostly-minus body (the compiler waits for each of its
-// loads before issuing the next; n = 8, d = 6: 0.97 against 0.47 ms per 2^20
-// points), while the two-lane kernel of the same (n, d) runs that metric
-// within a few percent of its own mostly-minus time: alternating-metric
-// launches take the two-lane kernel instead.
+// Without a pin of their own, alternating-metric launches take the
+// mostly-minus choice, except that a one-lane F_p register kernel is replaced
+// by the two-lane one of the same (n, d): the one-lane kernels' alternating
+// body runs about twice as long as their mostly-minus body (the compiler waits
+// for each of its loads before issuing the next; n = 8, d = 6: 0.97 against
+// 0.47 ms per 2^20 points), the two-lane kernel's within a few percent of its
+// own.
 static const Variant* alternating_variant(const Variant* v, int field, int n, int d) {
   if (!v || field != FIELD_FP || v->generic || v->L != 1) return v;
   const Variant* best = nullptr;
@@ -301,8 +321,11 @@ static const Variant* alternating_variant(const Variant* v, int field, int n, in
 int launch(int field, int n, int d, int64_t npts, int64_t ld, const void* momenta, const void* pols,
            void* out, uint8_t* status, const FpConst& fp, hipStream_t stream, int metric = BG_METRIC_MOSTLY_MINUS) {
   LaunchSpec spec;
-  const Variant* force =
-      metric == BG_METRIC_ALTERNATING ? alternating_variant(choose_variant(field, n, d), field, n, d) : nullptr;
+  const Variant* force = nullptr;
+  if (metric == BG_METRIC_ALTERNATING) {
+    const int idx = pinned(field, n, d, BG_METRIC_ALTERNATING);
+    force = idx >= 0 ? &registry()[idx] : alternating_variant(choose_variant(field, n, d), field, n, d);
+  }
   const int rc = prepare(field, n, d, npts, ld, momenta, pols, out, status, fp, spec, force);
   if (rc != BG_OK) return rc;
   spec.args.metric = metric;
@@ -430,18 +453,11 @@ int bg_variants(int field, int n, int d, bg_variant_info* out, int cap) {
 }
 
 int bg_select_variant(int field, int n, int d, int index) {
-  if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
-  if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
-  if (index >= 0 && (index >= (int)bg::registry().size() || !bg::fits(bg::registry()[index], field, n, d)))
-    return BG_EINVAL;
-  std::lock_guard<std::mutex> lk(bg::g_pin_mu);
-  for (auto it = bg::g_pins.begin(); it != bg::g_pins.end(); ++it)
-    if (it->field == field && it->n == n && it->d == d) {
-      bg::g_pins.erase(it);
-      break;
-    }
-  if (index >= 0) bg::g_pins.push_back({field, n, d, index});
-  return BG_OK;
+  return bg::select_variant(BG_METRIC_MOSTLY_MINUS, field, n, d, index);
+}
+
+int bg_select_variant_metric(int metric, int field, int n, int d, int index) {
+  return bg::select_variant(metric, field, n, d, index);
 }
 
 const char* bg_strerror(int code) {

@@ -39,7 +39,10 @@ struct Variant {
 inline bool fp_small_fold(const FpConst& k) { return k.c32 >= -(1 << 22) && k.c32 <= (1 << 22); }
 
 std::vector<Variant>& registry();
-bool is_pinned(int field, int n, int d);
+// pins per metric (BG_METRIC_*): pinned_index is -1 where none
+bool is_pinned(int field, int n, int d, int metric = BG_METRIC_MOSTLY_MINUS);
+int pinned_index(int field, int n, int d, int metric);
+int select_variant(int metric, int field, int n, int d, int index);
 
 // A fully prepared launch of one (field, n, d) batch: kernel, grid and the
 // argument block (kept alive by the owner, e.g. a graph plan).

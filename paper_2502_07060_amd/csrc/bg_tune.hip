@@ -48,23 +48,22 @@ struct DevBuf {
 
 }  // namespace
 
-extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps, double* ms_out,
-                           int cap, void* hip_stream) {
+extern "C" int bg_autotune_metric(int metric, int field, int n, int d, uint32_t p, int64_t npts, int reps,
+                                  double* ms_out, int cap, void* hip_stream) {
+  if (metric != BG_METRIC_MOSTLY_MINUS && metric != BG_METRIC_ALTERNATING) return BG_EINVAL;
   if (field != BG_FIELD_C128 && field != BG_FIELD_FP) return BG_EINVAL;
   if (n < 3 || n > BG_MAX_N || d < 1 || d > BG_MAX_D) return BG_EDOMAIN;
   if (npts <= 0 || reps <= 0) return BG_EINVAL;
   if (field == BG_FIELD_FP && (p < 3 || p >= 0x80000000u || !bg::is_prime_u32(p))) return BG_ENOTPRIME;
+  if (field == BG_FIELD_FP && metric == BG_METRIC_ALTERNATING && p % 4 != 1) return BG_EDOMAIN;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int count = bg_variants(field, n, d, nullptr, 0);
   if (count <= 0) return count < 0 ? count : BG_ENOTIMPL;
   std::vector<bg_variant_info> vs(count);
   bg_variants(field, n, d, vs.data(), count);
-  // the current pin, restored if tuning fails (a pinned variant stays
-  // pinned; an unpinned (field, n, d) stays on its default)
-  int prev = -1;
-  if (bg::is_pinned(field, n, d))
-    for (const auto& v : vs)
-      if (v.selected) prev = v.index;
+  // the current pin of this metric, restored if tuning fails (a pinned
+  // variant stays pinned; an unpinned (field, n, d) stays on its default)
+  const int prev = bg::pinned_index(field, n, d, metric);
 
   const size_t elem = field == BG_FIELD_FP ? 4 : 16;
   const int64_t nelem = (int64_t)n * d * npts;
@@ -86,15 +85,15 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
   }
   auto run = [&]() {
     if (field == BG_FIELD_FP)
-      return bg_amplitudes_fp(n, d, npts, npts, p, (const uint32_t*)mom.p, (const uint32_t*)pol.p,
-                              (uint32_t*)out.p, (uint8_t*)sta.p, st);
-    return bg_amplitudes_c128(n, d, npts, npts, (const double*)mom.p, (const double*)pol.p, (double*)out.p,
-                              (uint8_t*)sta.p, st);
+      return bg_amplitudes_fp_metric(metric, n, d, npts, npts, p, (const uint32_t*)mom.p, (const uint32_t*)pol.p,
+                                     (uint32_t*)out.p, (uint8_t*)sta.p, st);
+    return bg_amplitudes_c128_metric(metric, n, d, npts, npts, (const double*)mom.p, (const double*)pol.p,
+                                     (double*)out.p, (uint8_t*)sta.p, st);
   };
   int rc = BG_OK;
   // time of one launch of variant k, averaged over reps after a warm-up
   auto time_variant = [&](int k, double& per) {
-    bg_select_variant(field, n, d, vs[k].index);
+    bg::select_variant(metric, field, n, d, vs[k].index);
     rc = run();  // warm-up
     float ms = 0.f;
     if (rc == BG_OK && hipEventRecord(e0, st) != hipSuccess) rc = BG_EHIP;
@@ -134,31 +133,40 @@ extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, in
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != BG_OK || best < 0) {
-    bg_select_variant(field, n, d, prev);
+    bg::select_variant(metric, field, n, d, prev);
     return rc != BG_OK ? rc : BG_EHIP;
   }
-  bg_select_variant(field, n, d, best);
+  bg::select_variant(metric, field, n, d, best);
   return best;
 }
 
-// Selections as text, one line per pinned (field, n, d):
-//   field n d lanes comps_per_lane lds_tables generic padded max_d
+extern "C" int bg_autotune(int field, int n, int d, uint32_t p, int64_t npts, int reps, double* ms_out,
+                           int cap, void* hip_stream) {
+  return bg_autotune_metric(BG_METRIC_MOSTLY_MINUS, field, n, d, p, npts, reps, ms_out, cap, hip_stream);
+}
+
+// Selections as text, one line per pinned (field, n, d, metric):
+//   field n d lanes comps_per_lane lds_tables generic padded max_d metric
 // Lines name kernels by their shape, so a file stays valid across builds that
-// register kernels in another order; lines with no matching kernel are skipped.
+// register kernels in another order; lines with no matching kernel are
+// skipped, and a line without the metric column is a mostly-minus pin.
 extern "C" int bg_tune_save(const char* path) {
   if (!path) return BG_EINVAL;
   FILE* f = fopen(path, "w");
   if (!f) return BG_EINVAL;
-  fprintf(f, "# field n d lanes comps_per_lane lds_tables generic padded max_d\n");
+  fprintf(f, "# field n d lanes comps_per_lane lds_tables generic padded max_d metric\n");
   bg_variant_info vs[128];
   for (int field = 0; field <= 1; ++field)
     for (int n = 3; n <= BG_MAX_N; ++n)
       for (int d = 1; d <= BG_MAX_D; ++d) {
         const int c = std::min(128, bg_variants(field, n, d, vs, 128));
-        for (int k = 0; k < c; ++k)
-          if (vs[k].selected && bg::is_pinned(field, n, d))
-            fprintf(f, "%d %d %d %d %d %d %d %d %d\n", field, n, d, vs[k].lanes, vs[k].comps_per_lane,
-                    vs[k].lds_tables, vs[k].generic, vs[k].padded, vs[k].max_d);
+        for (int metric : {BG_METRIC_MOSTLY_MINUS, BG_METRIC_ALTERNATING}) {
+          const int idx = bg::pinned_index(field, n, d, metric);
+          for (int k = 0; k < c && idx >= 0; ++k)
+            if (vs[k].index == idx)
+              fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", field, n, d, vs[k].lanes, vs[k].comps_per_lane,
+                      vs[k].lds_tables, vs[k].generic, vs[k].padded, vs[k].max_d, metric);
+        }
       }
   fclose(f);
   return BG_OK;
@@ -172,15 +180,16 @@ extern "C" int bg_tune_load(const char* path) {
   int applied = 0;
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int field, n, d, lanes, dl, lt, gen, pad = 0, maxd = 0;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d %d", &field, &n, &d, &lanes, &dl, &lt, &gen, &pad, &maxd) < 7)
+    int field, n, d, lanes, dl, lt, gen, pad = 0, maxd = 0, metric = BG_METRIC_MOSTLY_MINUS;
+    if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &field, &n, &d, &lanes, &dl, &lt, &gen, &pad, &maxd,
+               &metric) < 7)
       continue;
     bg_variant_info vs[128];
     const int c = bg_variants(field, n, d, vs, 128);
     for (int k = 0; k < std::min(c, 128); ++k)
       if (vs[k].lanes == lanes && vs[k].comps_per_lane == dl && vs[k].lds_tables == lt && vs[k].generic == gen &&
           vs[k].padded == pad && (maxd == 0 || vs[k].max_d == maxd)) {
-        if (bg_select_variant(field, n, d, vs[k].index) == BG_OK) ++applied;
+        if (bg::select_variant(metric, field, n, d, vs[k].index) == BG_OK) ++applied;
         break;
       }
   }

@@ -259,18 +259,42 @@ def test_tune_save_and_load_roundtrip(tmp_path):
         pick = next((v for v in vs if v["generic"] and (v["padded"] or v["comps_per_lane"] < 6)), vs[-1])
         bg.bg_select_variant(field, n, d, pick["index"])
         picks[(field, n, d)] = pick["index"]
-    path = str(tmp_path / "tune.txt")
+    # an alternating-metric pin of its own, on another variant
+    ALT = bg.BG_METRIC_ALTERNATING
+    alt_pick = bg.bg_variants(bg.BG_FIELD_FP, 8, 6)[0]["index"]
+    bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, alt_pick, metric=ALT)
+    path, again = str(tmp_path / "tune.txt"), str(tmp_path / "again.txt")
     try:
         bg.bg_tune_save(path)
+        lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
+        assert sum(ln[-1] == str(ALT) for ln in lines) == 1
+        assert sum(ln[-1] == str(bg.BG_METRIC_MOSTLY_MINUS) for ln in lines) >= len(picks)
         for (field, n, d) in picks:
             bg.bg_select_variant(field, n, d, -1)
-        assert bg.bg_tune_load(path) >= len(picks)
+        bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, -1, metric=ALT)
+        assert bg.bg_tune_load(path) >= len(picks) + 1
         for (field, n, d), idx in picks.items():
             sel = [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]]
             assert sel == [idx], (field, n, d)
+        bg.bg_tune_save(again)  # the alternating pin came back too
+        assert open(again).read() == open(path).read()
     finally:
         for (field, n, d) in picks:
             bg.bg_select_variant(field, n, d, -1)
+        bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, -1, metric=ALT)
+
+
+def test_tune_load_reads_lines_without_metric(tmp_path):
+    """A selection line without the metric column pins the mostly-minus metric."""
+    v = bg.bg_variants(bg.BG_FIELD_FP, 8, 6)[-1]
+    path = tmp_path / "old.txt"
+    path.write_text("%d 8 6 %d %d %d %d %d %d\n" % (bg.BG_FIELD_FP, v["lanes"], v["comps_per_lane"],
+                                                     v["lds_tables"], v["generic"], v["padded"], v["max_d"]))
+    try:
+        assert bg.bg_tune_load(str(path)) == 1
+        assert [x["index"] for x in bg.bg_variants(bg.BG_FIELD_FP, 8, 6) if x["selected"]] == [v["index"]]
+    finally:
+        bg.bg_select_variant(bg.BG_FIELD_FP, 8, 6, -1)
 
 
 def test_failed_autotune_keeps_the_previous_pin():
@@ -292,6 +316,32 @@ def test_failed_autotune_keeps_the_previous_pin():
         assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == default
     finally:
         bg.bg_select_variant(field, n, d, -1)
+
+
+def test_metric_selection_and_tuning_arguments():
+    """Alternating-metric pins are separate from the mostly-minus ones (which
+    bg_variants reports), and the per-metric entry points reject an unknown
+    metric and, over Z_p, a prime with no square root of -1, before touching
+    the GPU."""
+    L = bg.lib()
+    field, n, d = bg.BG_FIELD_FP, 8, 6
+    vs = bg.bg_variants(field, n, d)
+    default = [v["index"] for v in vs if v["selected"]]
+    pick = next(v for v in vs if not v["selected"])
+    try:
+        bg.bg_select_variant(field, n, d, pick["index"], metric=bg.BG_METRIC_ALTERNATING)
+        assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == default
+        bg.bg_select_variant(field, n, d, -1, metric=bg.BG_METRIC_ALTERNATING)
+    finally:
+        bg.bg_select_variant(field, n, d, -1, metric=bg.BG_METRIC_ALTERNATING)
+    assert L.bg_select_variant_metric(7, field, n, d, -1) == bg.BG_EINVAL
+    assert L.bg_select_variant_metric(bg.BG_METRIC_ALTERNATING, field, n, d, 10**6) == bg.BG_EINVAL
+    assert L.bg_select_variant_metric(bg.BG_METRIC_ALTERNATING, field, 20, d, -1) == bg.BG_EDOMAIN
+    p = ctypes.c_uint32(2147483629)
+    assert L.bg_autotune_metric(7, field, n, d, p, 1024, 1, None, 0, None) == bg.BG_EINVAL
+    # 2^31 - 1 = 3 (mod 4): no square root of -1, so no alternating metric
+    assert L.bg_autotune_metric(bg.BG_METRIC_ALTERNATING, field, n, d, ctypes.c_uint32(2**31 - 1), 1024, 1,
+                                None, 0, None) == bg.BG_EDOMAIN
 
 
 def _bad_batch():

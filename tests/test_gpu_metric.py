@@ -42,11 +42,15 @@ def test_fp_every_variant(torch_dev, n, d):
     assert (st_o == 0).all()
     try:
         for v in bg.bg_variants(bg.BG_FIELD_FP, n, d):
-            bg.bg_select_variant(bg.BG_FIELD_FP, n, d, v["index"])
+            # the alternating metric's own pin: that variant's alternating body runs
+            bg.bg_select_variant(bg.BG_FIELD_FP, n, d, v["index"], metric=ALT)
             st_g, v_g = gpu_fp(torch_dev, k, e, P, metric=ALT)
             assert_fp_equal(st_g, v_g, st_o, v_o, f"alt fp n={n} d={d} variant {v}")
     finally:
-        bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1)
+        bg.bg_select_variant(bg.BG_FIELD_FP, n, d, -1, metric=ALT)
+    # unpinned: the mostly-minus choice (two lanes instead of one)
+    st_g, v_g = gpu_fp(torch_dev, k, e, P, metric=ALT)
+    assert_fp_equal(st_g, v_g, st_o, v_o, f"alt fp n={n} d={d} default")
 
 
 @pytest.mark.parametrize("n,d", [(4, 4), (5, 6), (8, 4), (8, 7), (9, 4), (10, 6), (11, 4), (14, 10)])
@@ -59,12 +63,12 @@ def test_c128_every_variant(torch_dev, n, d):
     st_o, v_o = bgtest.oracle_c(k, e, metric="alternating")
     try:
         for v in bg.bg_variants(bg.BG_FIELD_C128, n, d):
-            bg.bg_select_variant(bg.BG_FIELD_C128, n, d, v["index"])
+            bg.bg_select_variant(bg.BG_FIELD_C128, n, d, v["index"], metric=ALT)
             st_g, v_g = gpu_c(torch_dev, k, e, metric=ALT)
             assert np.array_equal(st_g, st_o)
             bgtest.check_c(v_g, v_o, k, e, label=f"alt c128 n={n} d={d} variant {v}", metric="alternating")
     finally:
-        bg.bg_select_variant(bg.BG_FIELD_C128, n, d, -1)
+        bg.bg_select_variant(bg.BG_FIELD_C128, n, d, -1, metric=ALT)
 
 
 def test_mostly_minus_tag_matches_plain_calls(torch_dev):
@@ -93,3 +97,25 @@ def test_alternating_statuses(torch_dev):
     assert st_o[3] == 2 and st_o[5] == 1
     st_g, v_g = gpu_fp(torch_dev, k, e, P, metric=ALT)
     assert_fp_equal(st_g, v_g, st_o, v_o, "alt statuses")
+
+
+def test_alternating_autotune_pins_its_own_variant(torch_dev):
+    """bg_autotune_metric in the alternating metric pins a variant for that
+    metric only: the mostly-minus selection is untouched, and both metrics
+    still match the oracle."""
+    n, d = 8, 10
+    field = bg.BG_FIELD_FP
+    k, e = fp_inputs(n, d, 40, 77)
+    before = [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]]
+    try:
+        chosen, timed = bg.bg_autotune(field, n, d, P, npts=1 << 14, reps=2, metric=ALT)
+        assert chosen in [v["index"] for v, _ in timed] and all(ms > 0 for _, ms in timed)
+        assert [v["index"] for v in bg.bg_variants(field, n, d) if v["selected"]] == before
+        st_o, v_o = bgtest.oracle_fp(k, e, P, metric="alternating")
+        st_g, v_g = gpu_fp(torch_dev, k, e, P, metric=ALT)
+        assert_fp_equal(st_g, v_g, st_o, v_o, "alt after tuning")
+        st_m, v_m = bgtest.oracle_fp(k, e, P)
+        st_h, v_h = gpu_fp(torch_dev, k, e, P)
+        assert_fp_equal(st_h, v_h, st_m, v_m, "mostly-minus after alt tuning")
+    finally:
+        bg.bg_select_variant(field, n, d, -1, metric=ALT)
