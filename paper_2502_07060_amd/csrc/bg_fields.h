@@ -54,10 +54,17 @@ struct FpField {
   // negated, on group lane 0 only (z is added once per group): by R for a
   // balanced z, by 2^32 for a lazily reduced one
   int32_t zlift64, zlift32;
+  // zlift32 again, in a register the compiler cannot see is equal to it:
+  // otherwise it rewrites x zlift32 + y zlift32 as (x + y) zlift32 in 64 bits,
+  // a multi-instruction 64-bit product instead of two multiply-adds
+  int32_t zlift32w;
 
   __device__ FpField(const FpConst& c, int s)
       : k(c), time_lane(s == 0),
-        zlift64((L == 1 || s == 0) ? -c.c64 : 0), zlift32((L == 1 || s == 0) ? -c.c32 : 0) {}
+        zlift64((L == 1 || s == 0) ? -c.c64 : 0), zlift32((L == 1 || s == 0) ? -c.c32 : 0),
+        zlift32w(zlift32) {
+    asm volatile("" : "+v"(zlift32w));
+  }
 
   __device__ __forceinline__ E prime0(E x) const {
     if constexpr (L == 1) return -x;
@@ -184,6 +191,28 @@ struct FpField {
     return finish_dot<LAZY>(t, u + uz_units(UZ));
   }
 
+  // -(x.y) - z - w: ndot_sub with a second term w, a balanced scalar that
+  // carries the factor of the lazy ones (lifted by 2^32 mod p like a lazy z)
+  template <int UX = 2, int UZ = 2, bool LAZY = false>
+  __device__ __forceinline__ S ndot_sub2(const E* xp, const E* y, S z, S w) const {
+    static_assert(UZ == 2 || UZ == 3, "z is balanced or lazily reduced");
+    A t = 0;
+    int u = 0;
+    acc_dot<UX>(t, u, xp, y);
+    if (u + uz_units(UZ) > kMaxU) {
+      t = fp_fold(t, k);
+      u = kFoldU;
+    }
+    t = mad64(z, UZ == 3 ? zlift32 : zlift64, t);
+    u += uz_units(UZ);
+    if (u + uz_units(3) > kMaxU) {
+      t = fp_fold(t, k);
+      u = kFoldU;
+    }
+    t = mad64(w, zlift32w, t);
+    return finish_dot<LAZY>(t, u + uz_units(3));
+  }
+
   __device__ __forceinline__ void axpy(A* K, S c, const E* v) const {
 #pragma unroll
     for (int i = 0; i < DL; ++i) K[i] = mad64(c, v[i], K[i]);
@@ -302,6 +331,15 @@ struct C128Field {
   template <int UX = 2, bool LAZY = false>
   __device__ __forceinline__ S ndot(const E* xp, const E* y) const {
     cplx t = cmul(xp[0], y[0]);
+#pragma unroll
+    for (int c = 1; c < DL; ++c) t = cmad(xp[c], y[c], t);
+    return finish_dot(t);
+  }
+  // z + sum of x_c y_c over the point's lanes, for a z whose L-th part each
+  // lane holds (z / L, exact for L a power of two): the lanes start their
+  // partial sums from it, so no addition follows the group sum
+  __device__ __forceinline__ S ndot_from(const E* xp, const E* y, cplx zpart) const {
+    cplx t = cmad(xp[0], y[0], zpart);
 #pragma unroll
     for (int c = 1; c < DL; ++c) t = cmad(xp[c], y[c], t);
     return finish_dot(t);

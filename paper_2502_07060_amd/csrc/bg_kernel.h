@@ -281,8 +281,9 @@ struct Recursion {
     constexpr bool kFp = Fld::exact;
     E J[NCUR][DL];
     E epsn[DL];
-    // per-point scalars: -Dh(X) for |X| >= 2 (by propagator index), and on F_p
-    // nc(X) = -(P_X . J_X) (by range index) and the propagator inverses
+    // per-point scalars: -Dh(X) for |X| >= 2 (by propagator index; complex:
+    // -Dh(X) / L), and on F_p nc(X) = -(P_X . J_X) (by range index) and the
+    // propagator inverses
     Store<S, NP, LT> nDh;
     Store<S, kFp ? NCUR : 0, LT> nc;
     Store<S, kFp ? NP : 0, LT> inv;
@@ -401,9 +402,17 @@ struct Recursion {
         // c(B)) are read one split ahead, inside the previous split's
         // scheduling region: with one wave per SIMD the read latency is
         // otherwise exposed at the start of every split.
+        // The adjacent-pair terms -Dh(A) J_B and -Dh(B) J_A of the four-gluon
+        // vertex share the three-gluon axpys of J_B and J_A (complex, and the
+        // small-fold-constant F_p schedule, where the two extra products fit
+        // the scalars' budget)
+        constexpr bool kMergeDh = !kFp || Fld::kSC;
         struct SplitLds {
           E v[DL];
-          S ca, cb;
+          S ca, cb;  // F_p: c(A), c(B)
+          // merged schedule: -Dh(A), -Dh(B) where that part has two legs or
+          // more (complex: their L-th parts, see ndot_from)
+          S da, db;
         };
         auto lds_of = [&](auto tc) {
           constexpr int t = decltype(tc)::value;
@@ -414,6 +423,8 @@ struct Recursion {
             o.ca = nc.get(R::idx(i, t));
             o.cb = nc.get(R::idx(t + 1, j));
           }
+          if constexpr (kMergeDh && t > i) o.da = nDh.get(R::pidx(i, t));
+          if constexpr (kMergeDh && t + 1 < j) o.db = nDh.get(R::pidx(t + 1, j));
           return o;
         };
         SplitLds next = lds_of(std::integral_constant<int, i>{});
@@ -428,8 +439,14 @@ struct Recursion {
             // P_B.J_A = P_S.J_A - c(A),  P_A.J_B = P_S.J_B - c(B),
             // P_A - P_B = 2 Q_{t+1} - Q_i - Q_{j+1}
             // lazy P_S slots, lazy stored P_X.J_X, lazily reduced results
-            const S nc2 = F.template ndot_sub<4, 3, true>(Pp, J[ia], cur.ca);   // -(P_B.J_A)
-            const S nc3 = F.template ndot_sub<4, 3, true>(Pp, J[ib], cur.cb);   // -(P_A.J_B)
+            // -(P_B.J_A), merged: -(P_B.J_A) + Dh(A)
+            S nc2, nc3;
+            if constexpr (kMergeDh && t > i) nc2 = F.template ndot_sub2<4, 3, true>(Pp, J[ia], cur.ca, cur.da);
+            else nc2 = F.template ndot_sub<4, 3, true>(Pp, J[ia], cur.ca);
+            // -(P_A.J_B), merged: -(P_A.J_B) - Dh(B)
+            if constexpr (kMergeDh && t + 1 < j)
+              nc3 = F.template ndot_sub2<4, 3, true>(Pp, J[ib], cur.cb, F.sneg(cur.db));
+            else nc3 = F.template ndot_sub<4, 3, true>(Pp, J[ib], cur.cb);
             F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nDm), cur.v);          // times Q_{t+1}
             F.template kaxpy<Fld::kPLazy>(K, uK, F.sneg(nc2), J[ib]);
             F.template kaxpy<Fld::kPLazy>(K, uK, nc3, J[ia]);
@@ -437,8 +454,12 @@ struct Recursion {
           } else {
 #pragma unroll
             for (int c = 0; c < DL; ++c) PA[c] = (t == i) ? cur.v[c] : F.eadd(PA[c], cur.v[c]);
-            const S n2 = F.ndot(col[t + 1], J[ia]);        // -(P_B.J_A)
-            const S n3 = F.ndot(PA, J[ib]);                // -(P_A.J_B)
+            // -(P_B.J_A) + Dh(A) (negated below) and -(P_A.J_B) - Dh(B)
+            S n2, n3;
+            if constexpr (t > i) n2 = F.ndot_from(col[t + 1], J[ia], cneg(cur.da));
+            else n2 = F.ndot(col[t + 1], J[ia]);
+            if constexpr (t + 1 < j) n3 = F.ndot_from(PA, J[ib], cur.db);
+            else n3 = F.ndot(PA, J[ib]);
             E v[DL];
 #pragma unroll
             for (int c = 0; c < DL; ++c) v[c] = F.esub(PA[c], col[t + 1][c]);
@@ -471,7 +492,9 @@ struct Recursion {
           F.template kaxpy<Fld::kPBalDiff>(K, uK, nDhS, QQ);
           F.fixed_fold(K);
         } else {
-          nDhS = half_scalar(F, nDsum);
+          // stored as its L-th part (the splits that read it start their
+          // lanes' partial dot products from it)
+          nDhS = {(0.5 / L) * nDsum.re, (0.5 / L) * nDsum.im};
         }
         if constexpr (!root) nDh.set(R::pidx(i, j), nDhS);
 
@@ -490,17 +513,19 @@ struct Recursion {
           });
         });
         F.fixed_fold(K);
-        static_for<i + 1, j>([&](auto tc) {
-          constexpr int t = decltype(tc)::value;
-          F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(i, t)), J[R::idx(t + 1, j)]);
-          if constexpr ((t - i) % 5 == 4) F.fixed_fold(K);
-        });
-        F.fixed_fold(K);
-        static_for<i, j - 1>([&](auto sc) {
-          constexpr int s1 = decltype(sc)::value;
-          F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(s1 + 1, j)), J[R::idx(i, s1)]);
-          if constexpr ((s1 - i) % 5 == 4) F.fixed_fold(K);
-        });
+        if constexpr (!kMergeDh) {
+          static_for<i + 1, j>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(i, t)), J[R::idx(t + 1, j)]);
+            if constexpr ((t - i) % 5 == 4) F.fixed_fold(K);
+          });
+          F.fixed_fold(K);
+          static_for<i, j - 1>([&](auto sc) {
+            constexpr int s1 = decltype(sc)::value;
+            F.template kaxpy<Fld::kPBal>(K, uK, nDh.get(R::pidx(s1 + 1, j)), J[R::idx(i, s1)]);
+            if constexpr ((s1 - i) % 5 == 4) F.fixed_fold(K);
+          });
+        }
 
         if constexpr (!root) {
           // J(S) = K' * 2/P_S^2

@@ -444,6 +444,20 @@ class FieldModelSC:
         t = self.B.chk(t + bz * lift, "ndot_sub lift")
         return self.finish_dot(t, u + uz, lazy)
 
+    def ndot_sub2(self, bx, by, bz, bw, UX=2, UZ=2, lazy=False):
+        """ndot_sub with a second, balanced term w lifted by 2^32 mod p."""
+        t, u = self.acc_dot(0, 0, bx, by, UX)
+        uz = 1 if UZ == 3 else 64
+        if u + uz > self.MAXU:
+            t, u = self.B.fold(t), self.FOLDU
+        lift = abs(self.B.k.c32) if UZ == 3 else abs(self.B.k.c64)
+        t = self.B.chk(t + bz * lift, "ndot_sub2 lift z")
+        u += uz
+        if u + 1 > self.MAXU:
+            t, u = self.B.fold(t), self.FOLDU
+        t = self.B.chk(t + bw * abs(self.B.k.c32), "ndot_sub2 lift w")
+        return self.finish_dot(t, u + 1, lazy)
+
 
 class TrackedVec(Vec):
     """A current accumulator under the small-fold schedule (kaxpy)."""
@@ -491,8 +505,16 @@ def replay_register_kernel_sc(p, N, DL, L):
             nDacc, uD = 0, 0
             for t in range(i, j):
                 nDm = F.ndot(nb, nb, UX=2, lazy=True)
-                nc2 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
-                nc3 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
+                # -Dh(A) (t > i) and -Dh(B) (t + 1 < j), balanced, ride in the
+                # scalars of the J_B and J_A axpys
+                if t > i:
+                    nc2 = F.ndot_sub2(lazyP, nb, nc, h, UX=4, UZ=3, lazy=True)
+                else:
+                    nc2 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
+                if t + 1 < j:
+                    nc3 = F.ndot_sub2(lazyP, nb, nc, h, UX=4, UZ=3, lazy=True)
+                else:
+                    nc3 = F.ndot_sub(lazyP, nb, nc, UX=4, UZ=3, lazy=True)
                 assert max(nDm, nc2, nc3) <= nb
                 K.kaxpy(66, nDm, h)       # times Q_{t+1} (balanced)
                 K.kaxpy(66, nc2, nb)      # times J_B
@@ -507,10 +529,6 @@ def replay_register_kernel_sc(p, N, DL, L):
                 for t in range(s1 + 1, j):
                     ne = F.ndot(nb, nb, UX=2, lazy=True)
                     K.kaxpy(66, ne, nb)
-            for _t in range(i + 1, j):
-                K.kaxpy(65, h, nb)        # nDh (balanced) times J
-            for _s1 in range(i, j - 1):
-                K.kaxpy(65, h, nb)
             if not root:
                 s = B.redc1(B.fold(K.b))                  # finish_mul32, small fold
                 J = B.redc1(B.fold(B.chk(s * inv, "finish product")))
