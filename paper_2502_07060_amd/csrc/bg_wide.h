@@ -273,6 +273,9 @@ struct WideRecursion {
       }
     }
     if (ln == 0) *flags = 0u;
+    if constexpr (!kFp) {
+      if (ln < N) nDht[rid(ln, ln)] = S{};  // a single leg has no two-way split
+    }
     group_sync();
     if (ln < DMAX) {  // prefix sums, one component per lane: all legs read first
       E k[kLegs];
@@ -382,9 +385,13 @@ struct WideRecursion {
       F.fold(K);
       nDs = fp_fold(mad64(nDm, F.k.inv2, nDs), F.k);
     } else {
+      // the adjacent-pair terms -Dh(A) J_B and -Dh(B) J_A join the scalars
+      // of the J_B and J_A axpys: the lanes of the item start their partial
+      // dot products from their share of -Dh (the table holds -Dh / LC, zero
+      // for a single leg)
       E v[DL];
-      const S n2 = F.ndot(PB, JA);
-      const S n3 = F.ndot(PA, JB);
+      const S n2 = F.ndot_from(PB, JA, cneg(nDht[ra]));  // -(P_B.J_A) + Dh(A), negated below
+      const S n3 = F.ndot_from(PA, JB, nDht[rb]);        // -(P_A.J_B) - Dh(B)
 #pragma unroll
       for (int x = 0; x < DL; ++x) v[x] = F.esub(PA[x], PB[x]);
       v[0] = F.prime0(v[0]);  // P_A - P_B
@@ -393,9 +400,11 @@ struct WideRecursion {
       F.axpy(K, n3, JA);
       nDs = cadd(nDs, nDm);
     }
-    // adjacent-pair terms of the four-gluon vertex that involve this cut
-    if (c >= i + 1) F.axpy(K, nDht[ra], JB);
-    if (c <= j - 2) F.axpy(K, nDht[rb], JA);
+    if constexpr (kFp) {
+      // adjacent-pair terms of the four-gluon vertex that involve this cut
+      if (c >= i + 1) F.axpy(K, nDht[ra], JB);
+      if (c <= j - 2) F.axpy(K, nDht[rb], JA);
+    }
     F.fold(K);
   }
 
@@ -525,7 +534,8 @@ struct WideRecursion {
             F.axpy(K, nDhS, QQ);
             F.fold(K);
           } else {
-            nDhS = Rec::half_scalar(F, nDs);
+            constexpr double kPart = 0.5 / Fld::kL;  // -Dh(S) / LC, the lanes' share
+            nDhS = cplx{kPart * nDs.re, kPart * nDs.im};
           }
           if (m < N) {
             nDht[id] = nDhS;
