@@ -54,16 +54,16 @@ struct FpField {
   // negated, on group lane 0 only (z is added once per group): by R for a
   // balanced z, by 2^32 for a lazily reduced one
   int32_t zlift64, zlift32;
-  // zlift32 again, in a register the compiler cannot see is equal to it:
-  // otherwise it rewrites x zlift32 + y zlift32 as (x + y) zlift32 in 64 bits,
-  // a multi-instruction 64-bit product instead of two multiply-adds
-  int32_t zlift32w;
+  // zlift64 and zlift32 again, in registers the compiler cannot see are
+  // equal to them: otherwise it rewrites x c + y c as (x + y) c in 64 bits, a
+  // multi-instruction 64-bit product instead of two multiply-adds
+  int32_t zlift64w, zlift32w;
 
   __device__ FpField(const FpConst& c, int s)
       : k(c), time_lane(s == 0),
         zlift64((L == 1 || s == 0) ? -c.c64 : 0), zlift32((L == 1 || s == 0) ? -c.c32 : 0),
-        zlift32w(zlift32) {
-    asm volatile("" : "+v"(zlift32w));
+        zlift64w(zlift64), zlift32w(zlift32) {
+    asm volatile("" : "+v"(zlift64w), "+v"(zlift32w));
   }
 
   __device__ __forceinline__ E prime0(E x) const {
@@ -191,10 +191,12 @@ struct FpField {
     return finish_dot<LAZY>(t, u + uz_units(UZ));
   }
 
-  // -(x.y) - z - w: ndot_sub with a second term w, a balanced scalar that
-  // carries the factor of the lazy ones (lifted by 2^32 mod p like a lazy z)
-  template <int UX = 2, int UZ = 2, bool LAZY = false>
+  // -(x.y) - z - w: ndot_sub with a second term w, a balanced scalar lifted
+  // like a z of class UW: by 2^32 mod p (UW = 3, w carrying the factor of the
+  // lazy scalars) or by R mod p (UW = 2, a plain balanced w)
+  template <int UX = 2, int UZ = 2, bool LAZY = false, int UW = 3>
   __device__ __forceinline__ S ndot_sub2(const E* xp, const E* y, S z, S w) const {
+    static_assert(UW == 2 || UW == 3, "w is lifted by R or by 2^32");
     static_assert(UZ == 2 || UZ == 3, "z is balanced or lazily reduced");
     A t = 0;
     int u = 0;
@@ -205,12 +207,12 @@ struct FpField {
     }
     t = mad64(z, UZ == 3 ? zlift32 : zlift64, t);
     u += uz_units(UZ);
-    if (u + uz_units(3) > kMaxU) {
+    if (u + uz_units(UW) > kMaxU) {
       t = fp_fold(t, k);
       u = kFoldU;
     }
-    t = mad64(w, zlift32w, t);
-    return finish_dot<LAZY>(t, u + uz_units(3));
+    t = mad64(w, UW == 3 ? zlift32w : zlift64w, t);
+    return finish_dot<LAZY>(t, u + uz_units(UW));
   }
 
   __device__ __forceinline__ void axpy(A* K, S c, const E* v) const {

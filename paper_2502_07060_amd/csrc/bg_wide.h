@@ -273,9 +273,7 @@ struct WideRecursion {
       }
     }
     if (ln == 0) *flags = 0u;
-    if constexpr (!kFp) {
-      if (ln < N) nDht[rid(ln, ln)] = S{};  // a single leg has no two-way split
-    }
+    if (ln < N) nDht[rid(ln, ln)] = S{};  // a single leg has no two-way split
     group_sync();
     if (ln < DMAX) {  // prefix sums, one component per lane: all legs read first
       E k[kLegs];
@@ -375,18 +373,19 @@ struct WideRecursion {
     loadJ(rb, JB);
     const S nDm = F.ndot_u(JA, JB);  // -(J_A . J_B)
     if constexpr (kFp) {
+      // the adjacent-pair terms -Dh(A) J_B and -Dh(B) J_A join the scalars
+      // of the J_B and J_A axpys: -Dh (balanced, zero for a single leg),
+      // lifted by R, enters each dot product's accumulator before its REDC
       E Qt[DL];
       loadM(c + 1, Qt);
-      const S nc2 = F.template ndot_sub<4>(Pp, JA, nct[ra]);   // -(P_B . J_A)
-      const S nc3 = F.template ndot_sub<4>(Pp, JB, nct[rb]);   // -(P_A . J_B)
+      const S nc2 = F.template ndot_sub2<4, 2, false, 2>(Pp, JA, nct[ra], nDht[ra]);            // -(P_B.J_A) + Dh(A)
+      const S nc3 = F.template ndot_sub2<4, 2, false, 2>(Pp, JB, nct[rb], F.sneg(nDht[rb]));   // -(P_A.J_B) - Dh(B)
       F.axpy(K, F.sneg(nDm), Qt);
       F.axpy(K, F.sneg(nc2), JB);
       F.axpy(K, nc3, JA);
-      F.fold(K);
       nDs = fp_fold(mad64(nDm, F.k.inv2, nDs), F.k);
     } else {
-      // the adjacent-pair terms -Dh(A) J_B and -Dh(B) J_A join the scalars
-      // of the J_B and J_A axpys: the lanes of the item start their partial
+      // the adjacent-pair terms: the lanes of the item start their partial
       // dot products from their share of -Dh (the table holds -Dh / LC, zero
       // for a single leg)
       E v[DL];
@@ -400,12 +399,7 @@ struct WideRecursion {
       F.axpy(K, n3, JA);
       nDs = cadd(nDs, nDm);
     }
-    if constexpr (kFp) {
-      // adjacent-pair terms of the four-gluon vertex that involve this cut
-      if (c >= i + 1) F.axpy(K, nDht[ra], JB);
-      if (c <= j - 2) F.axpy(K, nDht[rb], JA);
-    }
-    F.fold(K);
+    // F_p: K is folded by the caller, once after the item's cuts
   }
 
   // ---- four-gluon splits [i..c] | [c+1..t] | [t+1..j] of a pair of cuts --
@@ -499,6 +493,7 @@ struct WideRecursion {
             if (m < N) inv2 = invt[rid(i, j)];
             cut3(F, i, j, c1, Pp, Pp, Pp, K, nDs);
             if (c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, K, nDs);
+            F.fold(K);  // two cuts' products from zero fit the accumulator
           } else {
             E Qih[DL], Qil[DL], Qjh[DL], Qjl[DL], Qch[DL], Qcl[DL], PA[DL], PB[DL];
             loadQ(i, Qih, Qil);

@@ -304,6 +304,20 @@ class FieldModel:
         t = self.B.chk(t + bz * lift, "ndot_sub lift")
         return self.finish_dot(t, u + UZ, lazy)
 
+    def ndot_sub2(self, bx, by, bz, bw, UX=2, UZ=2, UW=2, lazy=False):
+        """ndot_sub with a second term w, lifted by R (UW = 2) or 2^32 (UW = 3)."""
+        t, u = self.acc_dot(0, 0, bx, by, UX)
+        if u + UZ > self.MAXU:
+            t, u = self.B.fold(t), 4
+        lift = abs(self.B.k.c32) if UZ == 3 else abs(self.B.k.c64)
+        t = self.B.chk(t + bz * lift, "ndot_sub2 lift z")
+        u += UZ
+        if u + UW > self.MAXU:
+            t, u = self.B.fold(t), 4
+        lift = abs(self.B.k.c32) if UW == 3 else abs(self.B.k.c64)
+        t = self.B.chk(t + bw * lift, "ndot_sub2 lift w")
+        return self.finish_dot(t, u + UW, lazy)
+
 
 class Vec:
     """An accumulator vector K (every component has the same bound)."""
@@ -618,16 +632,14 @@ def replay_lane_group_kernel(p, N, DL, LC):
         nDs = 0
         for _cut in range(2):
             nDm = F.ndot(h, h)
-            nc2 = F.ndot_sub(lazyP, h, nc, UX=4)
-            nc3 = F.ndot_sub(lazyP, h, nc, UX=4)
+            # -Dh of the parts (balanced) ride in the scalars, lifted by R
+            nc2 = F.ndot_sub2(lazyP, h, nc, h, UX=4)
+            nc3 = F.ndot_sub2(lazyP, h, nc, h, UX=4)
             Kp.axpy(nDm, h)
             Kp.axpy(nc2, h)
             Kp.axpy(nc3, h)
-            Kp.fold()
             nDs = B.fold(B.chk(nDs + nDm * h, "nDs"))  # folded after every cut
-            Kp.axpy(h, h)                         # adjacent-pair terms
-            Kp.axpy(h, h)
-            Kp.fold()
+        Kp.fold()                                 # once after the item's cuts
         cnt = 0
         for _q in range(max(0, m - 2)):           # four-gluon splits of the item
             ne = F.ndot(h, h)
