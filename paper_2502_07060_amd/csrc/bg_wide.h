@@ -485,12 +485,17 @@ struct WideRecursion {
         // loads and the division overlap their work
         E Pp[DL], QQ[DL];
         S inv2{};
+        if constexpr (kFp) {
+          // every slot of the range finishes some of its components
+          if (r < nr) {
+            lazyPQ(F, r, r + m - 1, Pp, QQ);
+            if (m < N) inv2 = invt[rid(r, r + m - 1)];
+          }
+        }
         if (act) {
           const int i = r, j = r + m - 1;
           const int c1 = i + u, c2 = j - 1 - u;
           if constexpr (kFp) {
-            lazyPQ(F, i, j, Pp, QQ);
-            if (m < N) inv2 = invt[rid(i, j)];
             cut3(F, i, j, c1, Pp, Pp, Pp, K, nDs);
             if (c2 != c1) cut3(F, i, j, c2, Pp, Pp, Pp, K, nDs);
             F.fold(K);  // two cuts' products from zero fit the accumulator
@@ -518,6 +523,13 @@ struct WideRecursion {
             }
           }
           cut4(F, i, j, c1, c2, K);
+        }
+        if constexpr (kFp) {
+          if (m < N) {
+            scalar_sum<LC>(F, nDs, lg);
+            if (r < nr) rs_finish<LC, DL>(F, K, QQ, Pp, lg, 0, 1, nDs, inv2, rid(r, r + m - 1), u == 0, lg);
+            continue;
+          }
         }
         range_sum(F, K, nDs, per);
         if (act && u == 0) {  // the range's first item finishes it
@@ -562,6 +574,86 @@ struct WideRecursion {
     if constexpr (kFp) fl |= bad >= (uint32_t)F.k.p ? 1u : 0u;
     if (fl) atomicOr(flags, fl);
     group_sync();
+  }
+
+  // ---- F_p, ranges shorter than the point: reduce-scatter, then a finish
+  // spread over the range's slots.  After the cuts every slot of a range
+  // holds partial sums of all DL components of K.  A step at lane distance
+  // ST halves what a slot holds: of each pair of components it keeps the one
+  // its bit selects, adding the partner's partial of it, and sends the other
+  // one.  After the steps a slot holds the complete sums of DN components of
+  // the lane's part (component cb + q cs); steps left when DN is odd add
+  // whole values.  Each slot then finishes its components; P_S . J_S is
+  // summed over the slots that hold different components.
+  template <int ST>
+  __device__ __forceinline__ void scalar_sum(const Fld& F, int64_t& x, int lg) const {
+    if constexpr (ST <= 32) {
+      if (lg > 0) {
+        x = fp_fold(x + lane_xor<ST>(x), F.k);
+        scalar_sum<ST * 2>(F, x, lg - 1);
+      }
+    }
+  }
+  template <int ST, int DN>
+  __device__ __forceinline__ void rest_sum(const Fld& F, A (&V)[DN], int lg) const {
+    if constexpr (ST <= 32) {
+      if (lg > 0) {
+#pragma unroll
+        for (int q = 0; q < DN; ++q) V[q] = add_acc(F, V[q], lane_xor<ST>(V[q]));
+        rest_sum<ST * 2, DN>(F, V, lg - 1);
+      }
+    }
+  }
+  template <int ST, int DN>
+  __device__ void rs_finish(const Fld& F, const A (&V)[DN], const E (&Qv)[DN], const E (&Pv)[DN], int lg, int cb,
+                            int cs, int64_t nDs, S inv2, int id, bool first, int lgall) const {
+    if constexpr (DN % 2 == 0 && ST <= 32) {
+      if (lg > 0) {
+        const bool b = (ln & ST) != 0;
+        A W[DN / 2];
+        E Qh[DN / 2], Ph[DN / 2];
+#pragma unroll
+        for (int p = 0; p < DN / 2; ++p) {
+          const A send = b ? V[2 * p] : V[2 * p + 1];
+          const A keep = b ? V[2 * p + 1] : V[2 * p];
+          W[p] = add_acc(F, keep, lane_xor<ST>(send));
+          Qh[p] = b ? Qv[2 * p + 1] : Qv[2 * p];
+          Ph[p] = b ? Pv[2 * p + 1] : Pv[2 * p];
+        }
+        rs_finish<ST * 2, DN / 2>(F, W, Qh, Ph, lg - 1, b ? cb + cs : cb, cs * 2, nDs, inv2, id, first, lgall);
+        return;
+      }
+    }
+    // after the lg steps left here, the 2^lg slots that differ only in the
+    // higher bits hold the same components
+    A K[DN];
+#pragma unroll
+    for (int q = 0; q < DN; ++q) K[q] = V[q];
+    rest_sum<ST, DN>(F, K, lg);
+    const S nDhS = fp_redc2(fp_fold(nDs, F.k), F.k);  // the cuts' sums already carry the factor 1/2
+    A t = 0;
+    int uu = 0;
+#pragma unroll
+    for (int q = 0; q < DN; ++q) {
+      // -Dh(S) (Q_i + Q_{j+1}), then J = K' 2/P_S^2
+      const E Jn = F.finish_mul32(fp_fold(mad64(nDhS, Qv[q], K[q]), F.k), inv2);
+      Jat(id, co + cb + q * cs) = Jn;
+      // P_S . J_S over this slot's components (an unreduced difference times
+      // a balanced value: the dot products' UX = 4 class)
+      if (uu + Fld::ux_units(4) > Fld::kMaxU) {
+        t = fp_fold(t, F.k);
+        uu = Fld::kFoldU;
+      }
+      t = mad64(Pv[q], Jn, t);
+      uu += Fld::ux_units(4);
+    }
+    t = fp_fold(t, F.k);
+    scalar_sum<LC>(F, t, lgall - lg);  // over the slots whose components differ
+    const S nc = F.template finish_dot<false>(t, Fld::kFoldU);
+    if (first) {
+      nct[id] = nc;
+      nDht[id] = nDhS;
+    }
   }
 
   // K + partial (F_p: both below 2^61 + 2^32 after their folds, refolded)

@@ -649,14 +649,26 @@ def replay_lane_group_kernel(p, N, DL, LC):
                 Kp.fold()
                 cnt = 0
         Kp.fold()
-        # the range's slots add their sums in a butterfly, refolding after
-        # every step (add_acc); every slot may hold a worst-case sum
+        # the range's slots add their sums, refolding after every step
+        # (add_acc): a butterfly for the root and for nDs, a reduce-scatter
+        # with the same per-step sums otherwise; every slot may hold a
+        # worst-case sum
         acc, nd = Kp.b, nDs
         s = 1
         while s < per:
             acc = B.fold(B.chk(acc + acc, "butterfly"))
             nd = B.fold(B.chk(nd + nd, "butterfly nDs"))
             s *= 2
+        # P_S . J_S of the spread finish: a slot's components (DL at most),
+        # folded, added over the slots with a refold per step, then the
+        # item's lanes and REDC2
+        t, _u = F.acc_dot(0, 0, lazyP, h, UX=4)
+        t = B.fold(t)
+        s = 1
+        while s < per:
+            t = B.fold(B.chk(t + t, "P.J over slots"))
+            s *= 2
+        assert F.finish_dot(t, 4, lazy=False) <= h
         B.redc2(B.fold(nd))
         K = Vec(B)
         K.b = acc
