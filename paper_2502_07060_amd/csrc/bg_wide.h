@@ -605,7 +605,7 @@ struct WideRecursion {
     }
   }
   template <int ST, int DN>
-  __device__ void rs_finish(const Fld& F, const A (&V)[DN], const E (&Qv)[DN], const E (&Pv)[DN], int lg, int cb,
+  __device__ __forceinline__ void rs_finish(const Fld& F, const A (&V)[DN], const E (&Qv)[DN], const E (&Pv)[DN], int lg, int cb,
                             int cs, int64_t nDs, S inv2, int id, bool first, int lgall) const {
     if constexpr (DN % 2 == 0 && ST <= 32) {
       if (lg > 0) {
@@ -617,8 +617,12 @@ struct WideRecursion {
           const A send = b ? V[2 * p] : V[2 * p + 1];
           const A keep = b ? V[2 * p + 1] : V[2 * p];
           W[p] = add_acc(F, keep, lane_xor<ST>(send));
-          Qh[p] = b ? Qv[2 * p + 1] : Qv[2 * p];
-          Ph[p] = b ? Pv[2 * p + 1] : Pv[2 * p];
+          // opaque copies: a select between two elements of one array would
+          // otherwise become an indexed load, with the array in scratch memory
+          E q0 = Qv[2 * p], q1 = Qv[2 * p + 1], p0 = Pv[2 * p], p1 = Pv[2 * p + 1];
+          asm volatile("" : "+v"(q0), "+v"(q1), "+v"(p0), "+v"(p1));
+          Qh[p] = b ? q1 : q0;
+          Ph[p] = b ? p1 : p0;
         }
         rs_finish<ST * 2, DN / 2>(F, W, Qh, Ph, lg - 1, b ? cb + cs : cb, cs * 2, nDs, inv2, id, first, lgall);
         return;
